@@ -1,0 +1,323 @@
+/*
+ * wmc_oracle.c -- plain, slow, double-precision reference ("oracle") for the
+ * discrete weighted mean curvature (WMC) of Gong & Goksel, "Weighted Mean
+ * Curvature" (arXiv 1903.07189), and for the iterations it drives.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this file; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it (through oracle/__init__.py).  It
+ * shares no code, header, table or constant with the HIP implementation.
+ *
+ * Everything is FP64, single threaded, scalar loops, written to be checked
+ * against the paper by eye:
+ *
+ *   O1  replicate (half-sample symmetric) extension of the image by one
+ *       pixel -- the Neumann condition of Sec. 4.1.2 and Sec. 3.3;
+ *   O2  the eight half-window responses d_i = h_i * U, Sec. 4.2 eq. (conv),
+ *       with the kernels exactly as printed there (kernel overlaid on the
+ *       image as printed, top row = previous image row), evaluated in the
+ *       "x12" domain S_i = 12 d_i so that all weights are integers;
+ *   O3  m = first index i (printed order 1..8) attaining min_i |S_i|,
+ *       Sec. 4.2 eq. (act);
+ *   O4  H_d = S_m / 12;
+ *   O5  one Jacobi update: data mode  U' = U + delta[(f - U) + lam H_d(U)]
+ *       (gradient descent of Sec. 5.2 with A = I and -dR/dU ~ H^w),
+ *       MCF mode U' = U + delta H_d(U)   (Sec. 3.5, eq. (MCF));
+ *   O6  a solve = iters applications of O5 starting from u0 (default f);
+ *   O7  diagnostic energies (eq. (wmcr) with q = 1, and eq. (areaReg));
+ *   O8  the adjoint of O5 and of a K-step solve (the paper leaves the
+ *       gradient of the regulariser to future work, end of Sec. 3, so this
+ *       is the exact derivative of the piecewise-linear update map with the
+ *       selection m held fixed);
+ *   O9  "listing mode": the Appendix A function's semantics (true 2-D
+ *       convolution, zero padding, its candidate order), for cross-checks.
+ *
+ * Images are row-major H x W arrays of doubles, x = column, y = row
+ * (downwards).  Functions never allocate more than O(H W) scratch.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Sec. 4.2: the eight half-window kernels h_1..h_8, times 12.
+ * [i][r][c]: r = 0 is the printed top row (image row y-1), c = 0 the
+ * printed left column (image column x-1). */
+static const int K12[8][3][3] = {
+    {{2, 2, 0}, {4, -12, 0}, {2, 2, 0}},  /* h1: left half window   */
+    {{2, 4, 2}, {2, -12, 2}, {0, 0, 0}},  /* h2: top                */
+    {{0, 2, 2}, {0, -12, 4}, {0, 2, 2}},  /* h3: right              */
+    {{0, 0, 0}, {2, -12, 2}, {2, 4, 2}},  /* h4: bottom             */
+    {{2, 4, 1}, {4, -12, 0}, {1, 0, 0}},  /* h5: top-left           */
+    {{1, 4, 2}, {0, -12, 4}, {0, 0, 1}},  /* h6: top-right          */
+    {{0, 0, 1}, {0, -12, 4}, {1, 4, 2}},  /* h7: bottom-right       */
+    {{1, 0, 0}, {4, -12, 0}, {2, 4, 1}},  /* h8: bottom-left        */
+};
+
+static int64_t clampi(int64_t v, int64_t lo, int64_t hi) {
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+/* Copies the 12x kernel table out (8*3*3 ints) so tests can inspect it. */
+void wmco_kernel_table(int* out) {
+    memcpy(out, K12, sizeof(K12));
+}
+
+/* O1: Ubar(y, x) for -1 <= y <= H, -1 <= x <= W via index clamping. */
+static double ubar(const double* U, int64_t H, int64_t W, int64_t y, int64_t x) {
+    return U[clampi(y, 0, H - 1) * W + clampi(x, 0, W - 1)];
+}
+
+/* O2: the eight candidates at pixel (y, x), in the difference form
+ * S_i = sum_{o != 0} c_i[o] (Ubar(x+o) - Ubar(x)); since the weights of
+ * every h_i sum to zero this equals sum_o c_i[o] Ubar(x+o) exactly in real
+ * arithmetic, and in FP64 it makes constant images give exactly 0. */
+static void candidates_at(const double* U, int64_t H, int64_t W, int64_t y, int64_t x,
+                          double S[8]) {
+    double c = U[y * W + x];
+    double nb[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) nb[r][q] = ubar(U, H, W, y + r - 1, x + q - 1) - c;
+    for (int i = 0; i < 8; ++i) {
+        double s = 0.0;
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q) {
+                if (r == 1 && q == 1) continue;
+                s += (double)K12[i][r][q] * nb[r][q];
+            }
+        S[i] = s;
+    }
+}
+
+/* O3: first index (0-based) attaining the minimum magnitude (strict '<'). */
+static int select_first_min(const double S[8]) {
+    int m = 0;
+    for (int i = 1; i < 8; ++i)
+        if (fabs(S[i]) < fabs(S[m])) m = i;
+    return m;
+}
+
+/* All eight candidates S_i (x12 domain) for every pixel: S[(y*W+x)*8 + i]. */
+void wmco_candidates(const double* U, int64_t H, int64_t W, double* S) {
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) candidates_at(U, H, W, y, x, S + (y * W + x) * 8);
+}
+
+/* O2-O4: H_d(U).  m_out (nullable) receives the 0-based selection. */
+void wmco_compute(const double* U, int64_t H, int64_t W, double* Hd, int8_t* m_out) {
+    double S[8];
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) {
+            candidates_at(U, H, W, y, x, S);
+            int m = select_first_min(S);
+            Hd[y * W + x] = S[m] / 12.0;
+            if (m_out) m_out[y * W + x] = (int8_t)m;
+        }
+}
+
+/* O5: one Jacobi step.  f == NULL selects MCF mode.  m_forced (nullable)
+ * replays a given selection instead of O3 (entries < 0 mean "use O3");
+ * m_out (nullable) records the selection actually used. */
+void wmco_step(const double* U, const double* f, int64_t H, int64_t W, double lam,
+               double delta, const int8_t* m_forced, double* Uout, int8_t* m_out) {
+    double S[8];
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) {
+            int64_t k = y * W + x;
+            candidates_at(U, H, W, y, x, S);
+            int m = (m_forced && m_forced[k] >= 0) ? m_forced[k] : select_first_min(S);
+            double hd = S[m] / 12.0;
+            if (f)
+                Uout[k] = U[k] + delta * ((f[k] - U[k]) + lam * hd);
+            else
+                Uout[k] = U[k] + delta * hd;
+            if (m_out) m_out[k] = (int8_t)m;
+        }
+}
+
+/* O6: iters Jacobi steps from u0 (NULL -> f).  f == NULL is MCF mode and
+ * then u0 must be given.  m_forced_all (nullable) holds iters selection maps
+ * back to back (H*W each) to replay. */
+void wmco_solve(const double* f, const double* u0, int64_t H, int64_t W, double lam,
+                double delta, int iters, const int8_t* m_forced_all, double* Uout) {
+    int64_t n = H * W;
+    double* a = (double*)malloc(sizeof(double) * n);
+    double* b = (double*)malloc(sizeof(double) * n);
+    memcpy(a, u0 ? u0 : f, sizeof(double) * n);
+    for (int t = 0; t < iters; ++t) {
+        wmco_step(a, f, H, W, lam, delta, m_forced_all ? m_forced_all + (int64_t)t * n : NULL, b,
+                  NULL);
+        double* tmp = a;
+        a = b;
+        b = tmp;
+    }
+    memcpy(Uout, a, sizeof(double) * n);
+    free(a);
+    free(b);
+}
+
+/* O7: eq. (wmcr) with q = 1 plus the quadratic data term (f NULL -> no data
+ * term): 1/2 sum (U-f)^2 + lam sum |H_d(U)|. */
+double wmco_energy_wmc(const double* U, const double* f, int64_t H, int64_t W, double lam) {
+    double e = 0.0, r = 0.0, S[8];
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) {
+            int64_t k = y * W + x;
+            if (f) e += 0.5 * (U[k] - f[k]) * (U[k] - f[k]);
+            candidates_at(U, H, W, y, x, S);
+            r += fabs(S[select_first_min(S)] / 12.0);
+        }
+    return e + lam * r;
+}
+
+/* O7: eq. (areaReg) discretised with forward differences (zero at the last
+ * column / row, i.e. replicate extension), plus the quadratic data term. */
+double wmco_energy_area(const double* U, const double* f, int64_t H, int64_t W, double lam) {
+    double e = 0.0, r = 0.0;
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) {
+            int64_t k = y * W + x;
+            if (f) e += 0.5 * (U[k] - f[k]) * (U[k] - f[k]);
+            double ux = (x + 1 < W) ? U[k + 1] - U[k] : 0.0;
+            double uy = (y + 1 < H) ? U[k + W] - U[k] : 0.0;
+            r += sqrt(1.0 + ux * ux + uy * uy);
+        }
+    return e + lam * r;
+}
+
+/* O9: Appendix A semantics.  The listing builds two base kernels (the
+ * left half window scaled to centre -6 and the top-left one scaled to
+ * centre -12), derives six more by left-right flip, transpose, up-down
+ * flip and 180-degree rotation, applies each by true 2-D convolution with
+ * zero padding ("same" size), and gathers the first-index minimum.  Here
+ * the eight listing kernels are derived from the two base kernels by the
+ * same geometric operations and applied as a convolution,
+ * out(y,x) = sum_{r,q} k[r][q] * u(y - (r-1), x - (q-1)), zero outside. */
+static void flip_lr(double k[3][3]) {
+    for (int r = 0; r < 3; ++r) { double t = k[r][0]; k[r][0] = k[r][2]; k[r][2] = t; }
+}
+static void flip_ud(double k[3][3]) {
+    for (int q = 0; q < 3; ++q) { double t = k[0][q]; k[0][q] = k[2][q]; k[2][q] = t; }
+}
+static void transpose3(double k[3][3]) {
+    for (int r = 0; r < 3; ++r)
+        for (int q = r + 1; q < 3; ++q) { double t = k[r][q]; k[r][q] = k[q][r]; k[q][r] = t; }
+}
+
+void wmco_listing_kernels(double out[8][3][3]) {
+    const double base1[3][3] = {{1, 1, 0}, {2, -6, 0}, {1, 1, 0}};
+    const double base2[3][3] = {{2, 4, 1}, {4, -12, 0}, {1, 0, 0}};
+    double k[3][3];
+    for (int slot = 0; slot < 8; ++slot) {
+        const double (*b)[3] = slot < 4 ? base1 : base2;
+        double scale = slot < 4 ? 6.0 : 12.0;
+        for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q) k[r][q] = b[r][q] / scale;
+        switch (slot) {
+            case 0: break;                              /* base1            */
+            case 1: flip_lr(k); break;                  /* lr-flip          */
+            case 2: transpose3(k); break;               /* transpose        */
+            case 3: transpose3(k); flip_ud(k); break;   /* ud-flip of transpose */
+            case 4: break;                              /* base2            */
+            case 5: flip_lr(k); break;                  /* lr-flip          */
+            case 6: flip_ud(k); break;                  /* ud-flip          */
+            case 7: flip_lr(k); flip_ud(k); break;      /* 180 degrees      */
+        }
+        memcpy(out[slot], k, sizeof(k));
+    }
+}
+
+void wmco_listing(const double* U, int64_t H, int64_t W, double* Hd, int8_t* m_out) {
+    double ks[8][3][3];
+    wmco_listing_kernels(ks);
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) {
+            double d[8];
+            for (int s = 0; s < 8; ++s) {
+                double acc = 0.0;
+                for (int r = 0; r < 3; ++r)
+                    for (int q = 0; q < 3; ++q) {
+                        int64_t yy = y - (r - 1), xx = x - (q - 1);
+                        if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                        acc += ks[s][r][q] * U[yy * W + xx];
+                    }
+                d[s] = acc;
+            }
+            int m = select_first_min(d);
+            Hd[y * W + x] = d[m];
+            if (m_out) m_out[y * W + x] = (int8_t)m;
+        }
+}
+
+/* O8: adjoint of one step (scatter-add form).  With m held fixed the step
+ * is affine in (U, f):
+ *   U'(x) = U(x) + delta[(f(x) - U(x)) + lam/12 sum_o c_m(x)[o] Ubar(x+o)]
+ * where c[o] includes the centre weight -12 and Ubar(x+o) is the clamped
+ * pixel.  Given gbar = dL/dU' this writes gU = dL/dU, adds delta*gbar into
+ * gf (nullable) and adds dL/dlam into *glam (nullable).  When
+ * delta_from_lam != 0 the step size is delta = 1/(1+lam) and its
+ * derivative -delta^2 enters dL/dlam.  f == NULL is MCF mode
+ * (U' = U + delta H_d, no lam).  m_forced as in wmco_step. */
+void wmco_step_adjoint(const double* U, const double* f, int64_t H, int64_t W, double lam,
+                       double delta, int delta_from_lam, const int8_t* m_forced,
+                       const double* gbar, double* gU, double* gf, double* glam) {
+    int64_t n = H * W;
+    double S[8];
+    double coef = f ? delta * lam / 12.0 : delta / 12.0;
+    double keep = f ? 1.0 - delta : 1.0;
+    for (int64_t k = 0; k < n; ++k) gU[k] = keep * gbar[k];
+    double gl = 0.0;
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) {
+            int64_t k = y * W + x;
+            candidates_at(U, H, W, y, x, S);
+            int m = (m_forced && m_forced[k] >= 0) ? m_forced[k] : select_first_min(S);
+            for (int r = 0; r < 3; ++r)
+                for (int q = 0; q < 3; ++q) {
+                    int64_t yy = clampi(y + r - 1, 0, H - 1), xx = clampi(x + q - 1, 0, W - 1);
+                    gU[yy * W + xx] += coef * (double)K12[m][r][q] * gbar[k];
+                }
+            if (f) {
+                double hd = S[m] / 12.0;
+                if (gf) gf[k] += delta * gbar[k];
+                double du_dlam = delta * hd;
+                if (delta_from_lam) du_dlam += -delta * delta * ((f[k] - U[k]) + lam * hd);
+                gl += gbar[k] * du_dlam;
+            }
+        }
+    if (glam) *glam += gl;
+}
+
+/* O8: adjoint of a K-step solve.  All K states are kept (small images
+ * only).  Outputs: gu0 = dL/dU^0 (nullable), gf = dL/df through the data
+ * term only (nullable; if the solve started from u0 = f the caller adds
+ * gu0), glam = dL/dlam (nullable).  UK (nullable) receives U^K. */
+void wmco_solve_adjoint(const double* f, const double* u0, int64_t H, int64_t W, double lam,
+                        double delta, int delta_from_lam, int K, const int8_t* m_forced_all,
+                        const double* gK, double* gu0, double* gf, double* glam, double* UK) {
+    int64_t n = H * W;
+    double* states = (double*)malloc(sizeof(double) * n * (size_t)(K + 1));
+    memcpy(states, u0 ? u0 : f, sizeof(double) * n);
+    for (int t = 0; t < K; ++t)
+        wmco_step(states + (int64_t)t * n, f, H, W, lam, delta,
+                  m_forced_all ? m_forced_all + (int64_t)t * n : NULL,
+                  states + (int64_t)(t + 1) * n, NULL);
+    if (UK) memcpy(UK, states + (int64_t)K * n, sizeof(double) * n);
+    double* g = (double*)malloc(sizeof(double) * n);
+    double* g2 = (double*)malloc(sizeof(double) * n);
+    memcpy(g, gK, sizeof(double) * n);
+    if (gf) memset(gf, 0, sizeof(double) * n);
+    double gl = 0.0;
+    for (int t = K - 1; t >= 0; --t) {
+        wmco_step_adjoint(states + (int64_t)t * n, f, H, W, lam, delta, delta_from_lam,
+                          m_forced_all ? m_forced_all + (int64_t)t * n : NULL, g, g2, gf, &gl);
+        double* tmp = g;
+        g = g2;
+        g2 = tmp;
+    }
+    if (gu0) memcpy(gu0, g, sizeof(double) * n);
+    if (glam) *glam = gl;
+    free(states);
+    free(g);
+    free(g2);
+}

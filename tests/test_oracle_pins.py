@@ -1,0 +1,590 @@
+"""Pins for the FP64 oracle: each test checks the oracle against something other
+than itself -- values the paper prints, closed forms derived from the printed
+kernels, invariants the paper states, or brute force -- so that a dropped
+term, a wrong sign, a transposed kernel or a wrong tie rule fails here.
+
+Notation: S_i = 12 d_i (the "x12 domain", integer weights), H_d = S_m / 12,
+x = column, y = row (downwards), the printed top kernel row sits on row y-1.
+"""
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_kernels(name):
+    """Parse a golden kernel file into {label: 3x3 Fraction array}."""
+    out, label, rows = {}, None, []
+    with open(os.path.join(GOLD, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            toks = line.split()
+            if len(toks) == 1 and not any(ch.isdigit() for ch in toks[0][:1]) and toks[0][0] != "-":
+                label, rows = toks[0], []
+                out[label] = rows
+            else:
+                rows.append([Fraction(t) for t in toks])
+    return out
+
+
+# ---------------------------------------------------------------------------------------
+# P1 -- the kernel table
+# ---------------------------------------------------------------------------------------
+
+def test_table_matches_printed_kernels():
+    """The oracle's x12 table equals the kernels printed in Sec. 4.2."""
+    printed = _read_kernels("half_window_kernels.txt")
+    table = oracle.kernel_table()
+    for i in range(8):
+        k = printed[f"h{i + 1}"]
+        for r in range(3):
+            for c in range(3):
+                assert Fraction(int(table[i, r, c]), 12) == k[r][c], (i, r, c)
+
+
+def _half_window_from_k4(direction):
+    """Build a half-window kernel from k4 alone (Neumann/reflection condition of
+    Sec. 4.1.2).  direction: normal (dy, dx) pointing *out of* the half window, one of
+    the 8 compass directions.  Taps with a positive component along the normal
+    are outside; their reflection across the line through the centre that is
+    perpendicular to the normal carries their weight inside."""
+    k4 = _read_kernels("laplace_kernels.txt")["k4"]
+    ny, nx = direction
+    out = [[Fraction(0)] * 3 for _ in range(3)]
+    for r in range(3):
+        for c in range(3):
+            oy, ox = r - 1, c - 1
+            dot = oy * ny + ox * nx
+            if dot <= 0:
+                out[r][c] += k4[r][c]
+            else:
+                # reflect o across the line perpendicular to n: o - 2 (o.n / n.n) n
+                nn = ny * ny + nx * nx
+                ry = oy - Fraction(2 * dot, nn) * ny
+                rx = ox - Fraction(2 * dot, nn) * nx
+                assert ry.denominator == 1 and rx.denominator == 1
+                out[int(ry) + 1][int(rx) + 1] += k4[r][c]
+    return out
+
+
+# outward normals: h1 left half window -> the cut removes the right column, etc.
+_OUTWARD = {
+    1: (0, 1),    # left window, right side cut away
+    2: (1, 0),    # top window, bottom cut away
+    3: (0, -1),   # right window
+    4: (-1, 0),   # bottom window
+    5: (1, 1),    # top-left window, bottom-right cut away
+    6: (1, -1),   # top-right window
+    7: (-1, -1),  # bottom-right window
+    8: (-1, 1),   # bottom-left window
+}
+
+
+@pytest.mark.parametrize("i", range(1, 9))
+def test_kernels_are_k4_with_reflection(i):
+    """Independent derivation: folding the most isotropic Laplacian k4 of
+    eq. (kernel3) onto each half window reproduces the table exactly."""
+    derived = _half_window_from_k4(_OUTWARD[i])
+    table = oracle.kernel_table()
+    for r in range(3):
+        for c in range(3):
+            assert Fraction(int(table[i - 1, r, c]), 12) == derived[r][c], (i, r, c)
+
+
+def test_table_structure():
+    t = oracle.kernel_table()
+    assert (t.sum(axis=(1, 2)) == 0).all()
+    assert (t[:, 1, 1] == -12).all()
+    assert ((t != 0).sum(axis=(1, 2)) == 6).all()           # six taps per half window
+    k4x12 = np.array([[1, 2, 1], [2, -12, 2], [1, 2, 1]])
+    for a, b in [(0, 2), (1, 3), (4, 6), (5, 7)]:           # opposite windows
+        s = t[a] + t[b]
+        off = np.ones((3, 3), bool)
+        off[1, 1] = False
+        assert (s[off] == 2 * k4x12[off]).all()
+        assert (t[a] == np.rot90(t[b], 2)).all()           # closed under 180 degrees
+
+
+def test_appendix_kernels_give_same_set():
+    """The Appendix A kernels (true convolution = correlation with the 180-degree
+    rotated kernel) are the printed set, in the order h3 h1 h4 h2 h7 h8 h6 h5."""
+    base = _read_kernels("appendix_base_kernels.txt")
+    lk = oracle.listing_kernels()
+    b1 = np.array([[float(v) for v in row] for row in base["base1"][:3]]) / 6.0
+    b2 = np.array([[float(v) for v in row] for row in base["base2"][:3]]) / 12.0
+    assert np.array_equal(lk[0], b1) and np.array_equal(lk[4], b2)
+    t = oracle.kernel_table() / 12.0
+    order = [3, 1, 4, 2, 7, 8, 6, 5]
+    for s in range(8):
+        assert np.allclose(np.rot90(lk[s], 2), t[order[s] - 1], atol=0, rtol=0), s
+
+
+# ---------------------------------------------------------------------------------------
+# P2 -- constants
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (6, 1), (2, 2), (5, 9), (17, 13)])
+def test_constant_gives_zero_everywhere(shape):
+    rng = np.random.default_rng(1)
+    for c in rng.uniform(-3, 3, size=4):
+        U = np.full(shape, c)
+        Hd = oracle.compute(U)
+        assert np.all(Hd == 0.0)
+        assert np.all(oracle.candidates(U) == 0.0)
+
+
+# ---------------------------------------------------------------------------------------
+# P3/P4 -- planes and quadratics: closed forms from the identities
+#   A  = 12 k4*U       = 4 Lap U = 8(a + c)
+#   E1 = (h1-k4)*U x12 = -8 U_x,  E2 = -8 U_y,
+#   E5 = -6 (U_x + U_y),          E6 = 6 (U_x - U_y)
+#   S = [A+E1, A+E2, A-E1, A-E2, A+E5, A+E6, A-E5, A-E6]
+# ---------------------------------------------------------------------------------------
+
+def _closed_form_candidates(a, b, c, d, e, y, x):
+    ux = 2 * a * x + b * y + d
+    uy = b * x + 2 * c * y + e
+    A = 8 * (a + c)
+    E1, E2, E5, E6 = -8 * ux, -8 * uy, -6 * (ux + uy), 6 * (ux - uy)
+    return [A + E1, A + E2, A - E1, A - E2, A + E5, A + E6, A - E5, A - E6]
+
+
+def _first_min(vals):
+    m = 0
+    for i in range(1, len(vals)):
+        if abs(vals[i]) < abs(vals[m]):
+            m = i
+    return m
+
+
+def _quadratic(a, b, c, d, e, g, H, W):
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    return a * x * x + b * x * y + c * y * y + d * x + e * y + g
+
+
+def test_quadratic_closed_form_all_candidates():
+    rng = np.random.default_rng(7)
+    H, W = 11, 13
+    for _ in range(40):
+        a, b, c, d, e, g = (int(v) for v in rng.integers(-3, 4, size=6))
+        U = _quadratic(a, b, c, d, e, g, H, W)
+        S = oracle.candidates(U)
+        Hd, m = oracle.compute(U, return_argmin=True)
+        for y in range(1, H - 1):
+            for x in range(1, W - 1):
+                want = _closed_form_candidates(a, b, c, d, e, y, x)
+                assert list(S[y, x]) == [float(v) for v in want], (a, b, c, d, e, y, x)
+                k = _first_min(want)
+                assert m[y, x] == k
+                assert Hd[y, x] == want[k] / 12.0
+
+
+def test_plane_closed_form_and_tie_sign():
+    """General plane beta x + gamma y: |H_d| = min(2/3|b|, 2/3|g|, 1/2|b+g|, 1/2|b-g|)
+    in the interior; the sign is the lowest-index member of the tied set."""
+    H, W = 7, 8
+    vals = [Fraction(k, 4) for k in range(-12, 13)]
+    for beta in vals[::3]:
+        for gamma in vals[::2]:
+            U = _quadratic(0, 0, 0, float(beta), float(gamma), 0.25, H, W)
+            Hd = oracle.compute(U)
+            mag = min(Fraction(2, 3) * abs(beta), Fraction(2, 3) * abs(gamma),
+                      abs(beta + gamma) / 2, abs(beta - gamma) / 2)
+            cand = _closed_form_candidates(0, 0, 0, float(beta), float(gamma), 3, 3)
+            want = cand[_first_min(cand)] / 12.0
+            assert abs(want) == pytest.approx(float(mag), abs=1e-15)
+            inner = Hd[1:-1, 1:-1]
+            assert np.all(inner == want), (beta, gamma)
+
+
+def test_aligned_planes_are_zero():
+    H, W = 9, 9
+    for beta, gamma in [(0.5, 0), (0, -1.25), (0.75, 0.75), (-2, 2), (3, 0)]:
+        U = _quadratic(0, 0, 0, beta, gamma, 0.0, H, W)
+        assert np.all(oracle.compute(U)[1:-1, 1:-1] == 0.0)
+
+
+def test_paraboloid_worked_values():
+    """U = (x-cx)^2 + (y-cy)^2 around a pixel centre; hand-derived values at
+    offsets (dx, dy), including the exact opposite-sign tie at (2, 2) whose
+    canonical (first index) winner is h1 -> -4/3."""
+    H = W = 11
+    c = 5
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    U = (x - c) ** 2 + (y - c) ** 2
+    Hd, m = oracle.compute(U, return_argmin=True)
+    expect = {(0, 0): 4 / 3, (1, 0): 0.0, (2, 0): -2 / 3, (3, 0): 4 / 3, (1, 1): 0.0,
+              (2, 1): 0.0, (2, 2): -4 / 3}
+    for (dx, dy), v in expect.items():
+        assert Hd[c + dy, c + dx] == pytest.approx(v, abs=1e-15), (dx, dy)
+    assert m[c + 2, c + 2] == 0  # h1 wins the tie
+
+
+# ---------------------------------------------------------------------------------------
+# P5 -- spherical cap apex (all eight responses equal by symmetry)
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("R", [3.0, 10.0, 40.0])
+def test_spherical_cap_apex(R):
+    n = 5 if R < 4 else 7
+    c = n // 2
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    U = np.sqrt(R * R - (x - c) ** 2 - (y - c) ** 2)
+    S = oracle.candidates(U)[c, c]
+    want = (2 / 3) * (np.sqrt(R * R - 1) - R) + (1 / 3) * (np.sqrt(R * R - 2) - R)
+    assert np.allclose(S / 12.0, want, rtol=1e-12, atol=1e-14)
+    assert oracle.compute(U)[c, c] == pytest.approx(want, rel=1e-12)
+    if R == 10.0:
+        assert want == pytest.approx(-0.066919, abs=5e-7)
+    # "becomes the Laplace operator" at the extremum (Sec. 3.3): k4 applied there
+    k4 = np.array([[1, 2, 1], [2, -12, 2], [1, 2, 1]]) / 12.0
+    assert oracle.compute(U)[c, c] == pytest.approx(float((k4 * U[c - 1:c + 2, c - 1:c + 2]).sum()),
+                                                     rel=1e-12)
+
+
+# ---------------------------------------------------------------------------------------
+# P6 -- rectilinear shapes: the exact discrete form of sampling/scale invariance
+# ---------------------------------------------------------------------------------------
+
+def _rect(H, W, y0, y1, x0, x1, J, bg=0.0):
+    U = np.full((H, W), bg)
+    U[y0:y1, x0:x1] = bg + J
+    return U
+
+
+def test_rectangle_corners_only():
+    rng = np.random.default_rng(3)
+    for _ in range(25):
+        h, w = (int(v) for v in rng.integers(2, 9, size=2))
+        H, W = h + int(rng.integers(4, 8)), w + int(rng.integers(4, 8))
+        y0, x0 = int(rng.integers(2, H - h - 1)), int(rng.integers(2, W - w - 1))
+        J = float(rng.choice([0.5, -0.75, 1.0, 0.125, -2.0]))
+        U = _rect(H, W, y0, y0 + h, x0, x0 + w, J, bg=0.25)
+        Hd = oracle.compute(U)
+        corners = {(y0, x0), (y0, x0 + w - 1), (y0 + h - 1, x0), (y0 + h - 1, x0 + w - 1)}
+        for yy in range(H):
+            for xx in range(W):
+                want = -J / 6 if (yy, xx) in corners else 0.0
+                assert Hd[yy, xx] == pytest.approx(want, abs=1e-15), (yy, xx)
+        assert Hd.sum() == pytest.approx(-2 * J / 3, abs=1e-13)
+        assert np.abs(Hd).sum() == pytest.approx(2 * abs(J) / 3, abs=1e-13)
+
+
+@pytest.mark.parametrize("scale", [1, 2, 3, 5])
+def test_rectangle_total_invariant_under_upsampling(scale):
+    """Nearest-neighbour integer upsampling (a change of sampling rate and
+    scale of the same geometry) leaves sum |H_d| unchanged."""
+    U = _rect(12, 14, 3, 8, 4, 10, 1.0)
+    Uk = np.kron(U, np.ones((scale, scale)))
+    assert np.abs(oracle.compute(Uk)).sum() == pytest.approx(2 / 3, abs=1e-13)
+
+
+def test_diagonal_staircase_edge_zero():
+    H = W = 12
+    y, x = np.mgrid[0:H, 0:W]
+    for k in [6, 9, 13]:
+        # interior only: the replicate border bends a diagonal edge where it
+        # meets the image boundary
+        U = np.where(x + y >= k, 1.0, 0.0)
+        assert np.all(oracle.compute(U)[1:-1, 1:-1] == 0.0)
+        U2 = np.where(x - y >= k - 10, 0.5, -0.5)
+        assert np.all(oracle.compute(U2)[1:-1, 1:-1] == 0.0)
+
+
+@pytest.mark.parametrize("mcf", [False, True])
+def test_step_edges_are_fixed_points(mcf):
+    H, W = 10, 12
+    y, x = np.mgrid[0:H, 0:W]
+    # axis-aligned step edges stay straight under the replicate border
+    for U in [np.where(x >= 5, 1.0, 0.0), np.where(y >= 3, 0.75, 0.25)]:
+        out = oracle.solve(None if mcf else U, lam=2.0, iters=7, u0=U)
+        assert np.array_equal(out, U)
+    # a 45-degree edge meets the border at a bend; one step leaves every pixel
+    # at distance >= 2 from the border unchanged
+    U = np.where(x - y >= 2, 1.0, 0.0)
+    out = oracle.step(U, None if mcf else U, lam=2.0)
+    assert np.array_equal(out[2:-2, 2:-2], U[2:-2, 2:-2])
+
+
+# ---------------------------------------------------------------------------------------
+# P7 -- contrast equivariance (eq. (scale))
+# ---------------------------------------------------------------------------------------
+
+def test_contrast_equivariance_exact_for_powers_of_two():
+    rng = np.random.default_rng(5)
+    U = rng.uniform(0, 1, size=(15, 17))
+    Hd = oracle.compute(U)
+    for alpha in [2.0, 0.5, -1.0, -4.0, 0.125]:
+        assert np.array_equal(oracle.compute(alpha * U), alpha * Hd)
+
+
+def test_contrast_equivariance_general():
+    rng = np.random.default_rng(6)
+    U = rng.uniform(0, 1, size=(15, 17))
+    Hd = oracle.compute(U)
+    for alpha, c in [(3.7, 0.2), (-0.3, 5.0), (1e3, -7.0)]:
+        got = oracle.compute(alpha * U + c)
+        assert np.allclose(got, alpha * Hd, rtol=1e-9, atol=1e-12 * max(1, abs(alpha) + abs(c)))
+
+
+def test_solver_contrast_equivariance():
+    rng = np.random.default_rng(8)
+    f = rng.uniform(0, 1, size=(12, 10))
+    base = oracle.solve(f, lam=1.5, iters=9)
+    for alpha in [2.0, -0.5]:
+        assert np.array_equal(oracle.solve(alpha * f, lam=1.5, iters=9), alpha * base)
+    got = oracle.solve(3.0 * f + 0.7, lam=1.5, iters=9)
+    assert np.allclose(got, 3.0 * base + 0.7, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------------------
+# P8 -- the column/row-sum form agrees with the direct eight-kernel sum
+# ---------------------------------------------------------------------------------------
+
+def _ae_form(U):
+    """Appendix-B-style identities, written independently of the oracle:
+    column sums colW/colC/colE, row sums rowN/rowS, A = binomial - 16C,
+    E1 = colW-colE, E2 = rowN-rowS, E5 = (E1+E2)/2 + (N-S) + (W-E),
+    E6 = (E2-E1)/2 + (N-S) + (E-W)."""
+    P = np.pad(U, 1, mode="edge")
+    NW, N, NE = P[:-2, :-2], P[:-2, 1:-1], P[:-2, 2:]
+    Wv, C, E = P[1:-1, :-2], P[1:-1, 1:-1], P[1:-1, 2:]
+    SW, S, SE = P[2:, :-2], P[2:, 1:-1], P[2:, 2:]
+    colW, colC, colE = NW + 2 * Wv + SW, N + 2 * C + S, NE + 2 * E + SE
+    rowN, rowS = NW + 2 * N + NE, SW + 2 * S + SE
+    A = colW + 2 * colC + colE - 16 * C
+    E1, E2 = colW - colE, rowN - rowS
+    E5 = (E1 + E2) / 2 + (N - S) + (Wv - E)
+    E6 = (E2 - E1) / 2 + (N - S) + (E - Wv)
+    return np.stack([A + E1, A + E2, A - E1, A - E2, A + E5, A + E6, A - E5, A - E6], axis=-1)
+
+
+def test_ae_form_matches_direct_random():
+    rng = np.random.default_rng(9)
+    for shape in [(1, 1), (1, 5), (4, 1), (9, 14), (32, 31)]:
+        U = rng.uniform(0, 1, size=shape)
+        assert np.allclose(_ae_form(U), oracle.candidates(U), atol=1e-13, rtol=0)
+
+
+def test_ae_form_matches_direct_dyadic_exact():
+    rng = np.random.default_rng(10)
+    U = rng.integers(-64, 64, size=(20, 23)) / 16.0
+    assert np.array_equal(_ae_form(U), oracle.candidates(U))
+
+
+# ---------------------------------------------------------------------------------------
+# border rule and listing mode (reading of the Neumann condition vs. Appendix A)
+# ---------------------------------------------------------------------------------------
+
+def test_listing_mode_constant_corners():
+    """Zero padding (Appendix A) gives -c/6 at the four image corners of a
+    constant image and 0 elsewhere; the replicate border gives 0 everywhere."""
+    c = 0.75
+    U = np.full((6, 7), c)
+    Hd = oracle.listing(U)
+    want = np.zeros_like(U)
+    for yy, xx in [(0, 0), (0, 6), (5, 0), (5, 6)]:
+        want[yy, xx] = -c / 6
+    assert np.allclose(Hd, want, atol=1e-15)
+
+
+def test_listing_mode_interior_same_values():
+    """Away from the border both modes see the same eight responses, so the
+    selected magnitude agrees everywhere and the value wherever no opposite-
+    sign exact tie exists."""
+    rng = np.random.default_rng(11)
+    U = rng.uniform(0, 1, size=(16, 16))
+    a = oracle.compute(U)[1:-1, 1:-1]
+    b = oracle.listing(U)[1:-1, 1:-1]
+    assert np.allclose(np.abs(a), np.abs(b), atol=1e-15)
+    assert np.allclose(a, b, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------------------
+# P9 -- solver invariants
+# ---------------------------------------------------------------------------------------
+
+def test_maximum_principle():
+    rng = np.random.default_rng(12)
+    f = rng.uniform(0, 1, size=(24, 20))
+    u0 = rng.uniform(0.2, 0.9, size=f.shape)
+    for lam in [0.5, 1.0, 4.0]:
+        for delta in [1 / (1 + lam), 0.5 / (1 + lam)]:
+            U = u0.copy()
+            lo, hi = min(f.min(), u0.min()), max(f.max(), u0.max())
+            for _ in range(15):
+                U = oracle.step(U, f, lam, delta)
+                assert U.min() >= lo - 1e-15 and U.max() <= hi + 1e-15
+
+
+def test_lambda_zero_closed_form():
+    rng = np.random.default_rng(13)
+    f = rng.uniform(0, 1, size=(9, 9))
+    u0 = rng.uniform(0, 1, size=(9, 9))
+    for delta in [1.0, 0.5, 0.3]:
+        t = 6
+        got = oracle.solve(f, lam=0.0, iters=t, delta=delta, u0=u0)
+        assert np.allclose(got, f + (1 - delta) ** t * (u0 - f), atol=1e-14)
+
+
+def test_first_step_on_rectangle():
+    lam, J = 2.0, 1.0
+    U = _rect(14, 15, 4, 9, 3, 11, J)
+    delta = 1 / (1 + lam)
+    U1 = oracle.step(U, U, lam, delta)
+    diff = U1 != U
+    corners = [(4, 3), (4, 10), (8, 3), (8, 10)]
+    assert diff.sum() == 4
+    for c in corners:
+        assert U1[c] == pytest.approx(J - delta * lam * J / 6, abs=1e-15)
+
+
+def test_resume_is_exact():
+    rng = np.random.default_rng(14)
+    f = rng.uniform(0, 1, size=(18, 21))
+    full = oracle.solve(f, lam=1.0, iters=25)
+    part = oracle.solve(f, lam=1.0, iters=15, u0=oracle.solve(f, lam=1.0, iters=10))
+    assert np.array_equal(full, part)
+
+
+def test_mcf_shrinks_total_curvature_of_rectangle():
+    """MCF (eq. (MCF)) with small delta rounds rectangle corners: only the
+    corners move, towards the background, and no new extrema appear."""
+    U = _rect(12, 12, 3, 9, 3, 9, 1.0)
+    U1 = oracle.step(U, None, delta=0.5)
+    assert U1.max() <= 1.0 and U1.min() >= 0.0
+    assert (U1 != U).sum() == 4
+
+
+# ---------------------------------------------------------------------------------------
+# P10 -- the adjoint: dot-product test with frozen selection, finite differences
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mcf", [False, True])
+def test_adjoint_dot_product(mcf):
+    rng = np.random.default_rng(15)
+    for shape in [(1, 1), (1, 6), (5, 1), (7, 9), (12, 11)]:
+        U = rng.uniform(0, 1, size=shape)
+        f = None if mcf else rng.uniform(0, 1, size=shape)
+        lam, delta = 1.3, 0.37
+        _, m = oracle.step(U, f, lam, delta, return_argmin=True)
+        v = rng.standard_normal(shape)
+        w = rng.standard_normal(shape)
+        # the map is affine in U with m frozen: J v = step(U+v) - step(U)
+        Jv = oracle.step(U + v, f, lam, delta, m_forced=m) - oracle.step(U, f, lam, delta, m_forced=m)
+        gU, _, _ = oracle.step_adjoint(U, w, f, lam, delta, delta_from_lam=False, m_forced=m)
+        lhs, rhs = float((Jv * w).sum()), float((v * gU).sum())
+        assert lhs == pytest.approx(rhs, rel=1e-12, abs=1e-12)
+
+
+def _loss(UK, target):
+    return 0.5 * float(((UK - target) ** 2).sum())
+
+
+def test_adjoint_vs_finite_differences():
+    rng = np.random.default_rng(16)
+    H, W, K, lam = 8, 9, 6, 1.0
+    f = rng.uniform(0, 1, size=(H, W))
+    target = rng.uniform(0, 1, size=(H, W))
+    res = oracle.solve_adjoint(np.zeros((H, W)), f, lam, K)  # for UK
+    UK = res["UK"]
+    res = oracle.solve_adjoint(UK - target, f, lam, K)
+    gf_total = res["gf"] + res["gu0"]
+
+    def run(ff, ll):
+        return oracle.solve(ff, lam=ll, iters=K)
+
+    h = 1e-6
+    checked = 0
+    for _ in range(20):
+        y, x = int(rng.integers(H)), int(rng.integers(W))
+        fp, fm = f.copy(), f.copy()
+        fp[y, x] += h
+        fm[y, x] -= h
+        # skip perturbations that change a selection anywhere along the path
+        same = True
+        up, um = fp.copy(), fm.copy()
+        for _t in range(K):
+            _, mp = oracle.step(up, fp, lam, return_argmin=True)
+            _, mm = oracle.step(um, fm, lam, return_argmin=True)
+            if not np.array_equal(mp, mm):
+                same = False
+                break
+            up, um = oracle.step(up, fp, lam), oracle.step(um, fm, lam)
+        if not same:
+            continue
+        fd = (_loss(run(fp, lam), target) - _loss(run(fm, lam), target)) / (2 * h)
+        assert fd == pytest.approx(gf_total[y, x], rel=1e-5, abs=1e-8)
+        checked += 1
+    assert checked >= 10
+    fdl = (_loss(run(f, lam + h), target) - _loss(run(f, lam - h), target)) / (2 * h)
+    assert fdl == pytest.approx(res["glam"], rel=1e-5, abs=1e-8)
+
+
+def test_adjoint_fixed_delta_lambda_gradient():
+    """With an explicit step size (not 1/(1+lam)) only delta*H_d enters dL/dlam."""
+    rng = np.random.default_rng(17)
+    H, W, K = 7, 7, 4
+    f = rng.uniform(0, 1, size=(H, W))
+    target = rng.uniform(0, 1, size=(H, W))
+    lam, delta, h = 0.8, 0.3, 1e-6
+    UK = oracle.solve(f, lam=lam, iters=K, delta=delta)
+    res = oracle.solve_adjoint(UK - target, f, lam, K, delta=delta, delta_from_lam=False)
+    fd = (_loss(oracle.solve(f, lam=lam + h, iters=K, delta=delta), target)
+          - _loss(oracle.solve(f, lam=lam - h, iters=K, delta=delta), target)) / (2 * h)
+    assert fd == pytest.approx(res["glam"], rel=1e-5, abs=1e-9)
+
+
+# ---------------------------------------------------------------------------------------
+# brute force on tiny inputs: the selection is the first minimum in printed order
+# ---------------------------------------------------------------------------------------
+
+def test_selection_brute_force_small_integers():
+    """Every 3x3 neighbourhood with entries in {0, 1, 2} centred in a 3x3
+    image (borders replicate, so the centre's neighbourhood is the image):
+    H_d equals the first-minimum response computed straight from the
+    printed fractions."""
+    printed = _read_kernels("half_window_kernels.txt")
+    ks = [np.array([[float(v) for v in printed[f"h{i}"][r]] for r in range(3)]) for i in range(1, 9)]
+    rng = np.random.default_rng(18)
+    vals = rng.integers(0, 3, size=(4000, 3, 3)).astype(np.float64)
+    for U in vals:
+        d = [float((k * U).sum()) for k in ks]
+        want = d[_first_min([round(v * 12) for v in d])]
+        assert oracle.compute(U)[1, 1] == pytest.approx(want, abs=1e-14)
+
+
+# ---------------------------------------------------------------------------------------
+# energies along the iteration (reported, not assumed: the paper never claims a
+# monotone decrease).  On the piecewise-smooth noisy workloads both the WMC energy
+# (eq. (wmcr), q = 1, plus the data term) and the area energy (eq. (areaReg)) decrease
+# at every step up to FP64 rounding once the iteration has converged.
+# ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dscale", [1.0, 0.5])
+def test_energy_decreases_on_c1(dscale):
+    import wmc_synth
+    noisy, clean = wmc_synth.c1()
+    f = noisy[0].astype(np.float64)
+    lam = 1.0
+    delta = dscale / (1 + lam)
+    U = f.copy()
+    ew, ea = [oracle.energy_wmc(U, f, lam)], [oracle.energy_area(U, f, lam)]
+    for _ in range(50):
+        U = oracle.step(U, f, lam, delta)
+        ew.append(oracle.energy_wmc(U, f, lam))
+        ea.append(oracle.energy_area(U, f, lam))
+    ew, ea = np.array(ew), np.array(ea)
+    assert np.all(ew[1:] <= ew[:-1] * (1 + 1e-12))
+    assert np.all(ea[1:] <= ea[:-1] * (1 + 1e-12))
+    assert ew[-1] < 0.6 * ew[0]
+    # the denoised result is closer to the clean image than the input
+    c = clean[0].astype(np.float64)
+    assert np.sqrt(((U - c) ** 2).mean()) < 0.75 * np.sqrt(((f - c) ** 2).mean())
