@@ -1,0 +1,204 @@
+/*
+ * wmc.h -- C ABI of libwmc: the discrete weighted mean curvature ("Half Laplace
+ * Operator") of Gong & Goksel, "Weighted Mean Curvature" (arXiv 1903.07189),
+ * and the iterations it drives, on AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Images are planes of 32-bit floats.  A plane set is described by
+ *   wmc_shape: n planes of h rows by w columns; element (p, y, x) lives at
+ *   ptr[p*ps + y*ld + x] (ld >= w, ps >= (h-1)*ld + w when n > 1).  x is the
+ *   column, y the row (downwards).  Every array passed together with one
+ *   wmc_shape uses that same layout.
+ * - All data pointers are device pointers owned by the caller; the library
+ *   never frees them and never keeps them after the call returns (except as
+ *   keys of its launch-graph cache, see wmc_release).  `lam` is a device array
+ *   too, so a learned lambda needs no host round trip.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Calls only enqueue work: a kernel fault surfaces at the caller's next
+ *   synchronisation, not in the return code.
+ * - Every call returns WMC_OK or a negative status; wmc_last_error() gives a
+ *   thread-local message for the last failure.  Arguments are validated on the
+ *   host before anything is enqueued; a rejected call enqueues nothing.
+ * - Border rule: pixels outside the image take the value of the nearest image
+ *   pixel (replicate), the reading of the Neumann condition of Sec. 4.1.2.
+ * - Selection rule: among the eight half-window responses the one of least
+ *   magnitude wins; exact ties go to the lowest index in the printed order
+ *   h_1..h_8 (Sec. 4.2, eq. (act)).
+ * - Step size `dt`: dt > 0 is used as given; dt <= 0 selects the default,
+ *   1/(1+lam) with a data term (each update is then a convex combination of
+ *   f and the 3x3 neighbourhood) and 1 for the pure curvature flow.
+ * - Arithmetic is FP32; results are bitwise independent of the tiling,
+ *   temporal-blocking depth and batching chosen by the library.
+ * - The library runs on gfx950 only (WMC_EUNSUPPORTED elsewhere).
+ */
+#ifndef WMC_H
+#define WMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WMC_OK 0
+#define WMC_EINVAL (-1)       /* bad pointer, shape, stride, overlap or count      */
+#define WMC_EHIP (-2)         /* a HIP call failed (message has hipGetErrorString) */
+#define WMC_ENOMEM (-3)       /* caller workspace smaller than the size query says */
+#define WMC_EUNSUPPORTED (-4) /* current device is not gfx950                      */
+
+typedef struct wmc_shape {
+    int64_t n;  /* number of planes (>= 1)                  */
+    int64_t h;  /* rows per plane (>= 1)                     */
+    int64_t w;  /* columns per plane (>= 1)                  */
+    int64_t ld; /* row stride in elements (>= w)             */
+    int64_t ps; /* plane stride in elements                  */
+} wmc_shape;
+
+/* One image of an uneven batch: `channels` planes of h x w, each with row
+ * stride ld and plane stride ps (same layout for u0, f and out).  All its
+ * channels use lam[lam_index] (the paper smooths each colour channel
+ * separately with one setting, Sec. 5.4). */
+typedef struct wmc_image {
+    const float* u0; /* initial state, NULL -> start from f             */
+    const float* f;  /* data term, NULL -> pure curvature flow (needs u0) */
+    float* out;      /* result U^iters                                    */
+    int64_t h, w, ld, ps;
+    int32_t channels;
+    int32_t lam_index;
+} wmc_image;
+
+/* Launch shape of the fused solver.  Zero fields mean "choose". */
+typedef struct wmc_tuning {
+    int32_t cols;      /* columns per lane: 1, 2 or 4                              */
+    int32_t tsteps;    /* Jacobi sweeps per tile residency: 1, 2, 3, 4, 6 or 8       */
+    int32_t seg_rows;  /* output rows per work item (>= 1)                           */
+    int32_t use_graph; /* 1: replay a cached hipGraph of the launch sequence, 0: no  */
+} wmc_tuning;
+
+/* ---------------------------------------------------------------------------
+ * wmc_compute -- H_d(U): the Half Laplace Operator, Sec. 4.2 eqs. (conv) and
+ * (act).  For every pixel the eight half-window responses d_i = h_i * U are
+ * formed (kernels as printed, correlation, replicate border) and the response
+ * of least magnitude is written to hw.  u and hw share layout s and must not
+ * overlap.  Traffic: 4 B read + 4 B written per pixel.
+ * ------------------------------------------------------------------------- */
+int wmc_compute(const float* u, float* hw, wmc_shape s, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * wmc_step -- one synchronous (Jacobi) update, every pixel from the same U^t:
+ *   f != NULL:  U' = U + dt [ (f - U) + lam H_d(U) ]   gradient descent on
+ *               1/2||U - f||^2 + lam R_area with -dR/dU ~ H^w and A = I
+ *               (Sec. 5.2, Sec. 3.3);
+ *   f == NULL:  U' = U + dt H_d(U)                     curvature flow,
+ *               Sec. 3.5 eq. (MCF) (lam is ignored and may be NULL).
+ * lam: device array of s.n values, plane p uses lam[p] (lam >= 0).
+ * argmin_out: NULL, or a device byte map (layout s, 1 byte per element)
+ * receiving the 0-based index of the selected half window at every pixel.
+ * u_out must not overlap u, f or argmin_out.  12 B/pixel with f, 8 B without.
+ * ------------------------------------------------------------------------- */
+int wmc_step(const float* u, const float* f, float* u_out, const float* lam, float dt,
+             uint8_t* argmin_out, wmc_shape s, void* stream);
+
+/* Bytes of workspace wmc_solve needs (one extra plane set,
+ * wmc_set_stride(s) floats). */
+size_t wmc_solve_workspace(wmc_shape s);
+
+/* Elements between consecutive plane sets of a checkpoint buffer: n*ps, or
+ * (n-1)*ps + (h-1)*ld + w if that is larger (0 for an invalid shape). */
+int64_t wmc_set_stride(wmc_shape s);
+
+/* Number of checkpoint plane sets a solve of `iters` steps stores with
+ * checkpoints every `ckpt_every` steps: ceil(iters / ckpt_every). */
+int64_t wmc_num_checkpoints(int iters, int ckpt_every);
+
+/* ---------------------------------------------------------------------------
+ * wmc_solve -- `iters` applications of wmc_step, starting from u0 (NULL ->
+ * f), result in u_out.  The library fuses several sweeps per pass over
+ * memory (temporal blocking) and replays the launch sequence as a cached
+ * hipGraph; the result is bitwise the one of `iters` separate wmc_step calls.
+ * ckpt: NULL, or a device buffer of wmc_num_checkpoints(iters, ckpt_every)
+ * plane sets (plane set j at ckpt + j*wmc_set_stride(s), layout s) receiving
+ * U^{j*ckpt_every} -- the states wmc_backward restarts from.
+ * tune: NULL -> the autotuner's choice for this shape (cached), else used as
+ * given (zero fields filled in).  ws: device workspace of at least
+ * wmc_solve_workspace(s) bytes.  u_out must not overlap u0, f, ckpt or ws.
+ * iters == 0 copies u0 (or f) to u_out.
+ * ------------------------------------------------------------------------- */
+int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, int iters,
+              float dt, float* ckpt, int ckpt_every, const wmc_tuning* tune, void* ws,
+              size_t ws_bytes, wmc_shape s, void* stream);
+
+/* Bytes of workspace wmc_solve_batched needs for this batch. */
+size_t wmc_batched_workspace(const wmc_image* imgs, int n_imgs);
+
+/* ---------------------------------------------------------------------------
+ * wmc_solve_batched -- wmc_solve for many images of different sizes at once:
+ * every channel of every image gets `iters` updates (each image with its own
+ * lam[lam_index], channels independent, Sec. 5.4).  All tiles of all images
+ * form one work list consumed by a persistent launch per fused block of
+ * sweeps; the launch sequence is captured once into a hipGraph and replayed.
+ * imgs: HOST array of n_imgs descriptors (device pointers inside).  Outputs
+ * must not overlap any input or each other.  tune: NULL -> autotuned.
+ * ------------------------------------------------------------------------- */
+int wmc_solve_batched(const wmc_image* imgs, int n_imgs, const float* lam, int iters, float dt,
+                      const wmc_tuning* tune, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * wmc_autotune -- times candidate launch shapes (columns per lane, sweeps
+ * per residency, rows per work item) on this batch for a few iterations,
+ * using ws as scratch and writing nothing else, and returns the fastest in
+ * *out.  Results are cached in memory and in the JSON file named by the
+ * environment variable WMC_TUNE_CACHE (default ~/.cache/wmc/tune.json),
+ * keyed by device architecture and a size class of the batch.  The
+ * environment variable WMC_TUNE=off|cached|force selects defaults only,
+ * cached results or a fresh search.  Synchronises the stream.
+ * ------------------------------------------------------------------------- */
+int wmc_autotune(const wmc_image* imgs, int n_imgs, int iters, wmc_tuning* out, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/* Bytes of workspace wmc_backward needs. */
+size_t wmc_backward_workspace(wmc_shape s, int iters, int ckpt_every);
+
+/* ---------------------------------------------------------------------------
+ * wmc_backward -- reverse-mode derivative of L(U^iters) through a solve.
+ * The paper leaves the gradient of the WMC regulariser open (end of Sec. 3);
+ * this is the exact derivative of the update map of wmc_step with the
+ * selected half window held at its forward value:
+ *   dL/dU^t(y) = k dL/dU^{t+1}(y)
+ *              + c sum_{x,o : clamp(x+o) = y} h_{m(x)}[o] dL/dU^{t+1}(x)
+ * with k = 1 - dt, c = dt lam (data term) or k = 1, c = dt (flow),
+ * dL/df += dt dL/dU^{t+1}, and dL/dlam_p summed over the plane (including
+ * the dependence of the default dt = 1/(1+lam) on lam).
+ * f, u0, lam, iters, dt, ckpt_every: exactly as passed to the wmc_solve that
+ * produced `ckpt` (the checkpoints are restarted from and each segment of
+ * ckpt_every steps is recomputed).  g_out: dL/dU^iters.
+ * Outputs (device, layout s, overwritten):
+ *   g_f   (data term only; NULL allowed) dL/df, including the path through
+ *         U^0 = f when u0 == NULL;
+ *   g_u0  (NULL allowed) dL/dU^0 when u0 != NULL (or in flow mode);
+ *   g_lam (NULL allowed) n floats, dL/dlam_p.
+ * Deterministic: the lambda sums use a fixed reduction order, no atomics.
+ * ws: at least wmc_backward_workspace(s, iters, ckpt_every) bytes.
+ * ------------------------------------------------------------------------- */
+int wmc_backward(const float* f, const float* u0, const float* lam, int iters, float dt,
+                 const float* ckpt, int ckpt_every, const float* g_out, float* g_f, float* g_u0,
+                 float* g_lam, void* ws, size_t ws_bytes, wmc_shape s, void* stream);
+
+/* Checks on the current device that the wavefront lane shifts the kernels
+ * rely on move data as expected; returns WMC_OK or WMC_EHIP/WMC_EUNSUPPORTED.
+ * Synchronises the default stream. */
+int wmc_selftest(void);
+
+/* Thread-local description of the last failure ("" if none). */
+const char* wmc_last_error(void);
+
+/* Frees cached launch graphs, device-side work tables and tuning state. */
+void wmc_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WMC_H */

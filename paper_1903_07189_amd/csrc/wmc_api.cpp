@@ -1,0 +1,1214 @@
+// wmc_api.cpp -- host side of libwmc: the C ABI declared in include/wmc.h.
+//
+// Validates arguments on the host (before any HIP call), plans launch
+// sequences (temporal blocking depth per launch, ping-pong buffers,
+// checkpoints), captures them into cached hipGraphs, runs the autotuner and
+// drives the adjoint.  All device work is in wmc_stream.hip / wmc_adjoint.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include <sys/stat.h>
+#include <sys/types.h>
+
+#include "wmc.h"
+#include "wmc_internal.h"
+
+using namespace wmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(WMC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define WMC_HIP(call, what)                         \
+    do {                                            \
+        hipError_t _e = (call);                     \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+// WMC_FAULT_INJECT=launch|graph|alloc makes the named stage report a HIP
+// failure without touching the device (host-side error-path testing).
+bool injected(const char* stage) {
+    const char* v = std::getenv("WMC_FAULT_INJECT");
+    return v && std::strcmp(v, stage) == 0;
+}
+
+// ---------------------------------------------------------------------------
+// device checks
+// ---------------------------------------------------------------------------
+std::mutex g_mu;
+std::map<int, int> g_arch_ok;  // device -> 1 gfx950, 0 other
+std::map<int, int> g_num_cu;
+
+int check_device(int* dev_out) {
+    if (injected("launch")) return fail(WMC_EHIP, "injected launch failure (WMC_FAULT_INJECT)");
+    int dev = 0;
+    WMC_HIP(hipGetDevice(&dev), "hipGetDevice");
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_arch_ok.find(dev);
+        if (it == g_arch_ok.end()) {
+            hipDeviceProp_t prop;
+            WMC_HIP(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+            const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+            g_arch_ok[dev] = ok ? 1 : 0;
+            g_num_cu[dev] = prop.multiProcessorCount;
+            it = g_arch_ok.find(dev);
+        }
+        if (!it->second) return fail(WMC_EUNSUPPORTED, "libwmc runs on gfx950 (MI355X) only");
+    }
+    if (dev_out) *dev_out = dev;
+    return WMC_OK;
+}
+
+int num_cu(int dev) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_num_cu.find(dev);
+    return it == g_num_cu.end() ? 256 : it->second;
+}
+
+// ---------------------------------------------------------------------------
+// validation helpers
+// ---------------------------------------------------------------------------
+constexpr int64_t kMaxSide = (int64_t)1 << 30;
+
+int64_t extent_elems(const wmc_shape& s) { return (s.n - 1) * s.ps + (s.h - 1) * s.ld + s.w; }
+
+// Elements between consecutive plane sets in workspace / checkpoint buffers:
+// n*ps, or the extent of one plane set if that is larger.
+int64_t set_stride_elems(const wmc_shape& s) {
+    const int64_t e = extent_elems(s), np = s.n * s.ps;
+    return np >= e ? np : e;
+}
+
+int check_shape(const wmc_shape& s) {
+    if (s.n < 1 || s.h < 1 || s.w < 1) return fail(WMC_EINVAL, "shape: n, h and w must be >= 1");
+    if (s.h >= kMaxSide || s.w >= kMaxSide) return fail(WMC_EINVAL, "shape: h and w must be < 2^30");
+    if (s.n > 65535) return fail(WMC_EINVAL, "shape: at most 65535 planes per call");
+    if (s.ld < s.w) return fail(WMC_EINVAL, "shape: ld must be >= w");
+    if (s.n > 1 && s.ps < (s.h - 1) * s.ld + s.w)
+        return fail(WMC_EINVAL, "shape: ps must be >= (h-1)*ld + w when n > 1");
+    if (s.ps < 0) return fail(WMC_EINVAL, "shape: ps must be >= 0");
+    return WMC_OK;
+}
+
+struct Range {
+    uintptr_t lo, hi;  // [lo, hi)
+};
+
+Range range_of(const void* p, int64_t elems, int64_t elem_bytes) {
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+    return {lo, lo + (uintptr_t)(elems * elem_bytes)};
+}
+
+bool overlaps(const Range& a, const Range& b) {
+    if (!a.lo || !b.lo) return false;
+    return a.lo < b.hi && b.lo < a.hi;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool aligned_for(const void* p, int C) { return (reinterpret_cast<uintptr_t>(p) % (4 * C)) == 0; }
+
+// Largest C in {4, 2, 1} for which every buffer row starts 4C-aligned.
+int vec_cols(std::initializer_list<const void*> ptrs, int64_t ld, int64_t ps) {
+    for (int C : {4, 2}) {
+        bool ok = (ld % C == 0) && (ps % C == 0);
+        for (const void* p : ptrs)
+            if (p && !aligned_for(p, C)) ok = false;
+        if (ok) return C;
+    }
+    return 1;
+}
+
+bool valid_T(int T) { return T == 1 || T == 2 || T == 3 || T == 4 || T == 6 || T == 8; }
+
+// Splits a run of `len` sweeps into launches of at most T sweeps each, every
+// one a compiled depth.
+void split_run(int len, int T, std::vector<int>& out) {
+    static const int depths[] = {8, 6, 4, 3, 2, 1};
+    while (len > 0) {
+        int t = std::min(len, T);
+        for (int d : depths)
+            if (d <= t) {
+                t = d;
+                break;
+            }
+        out.push_back(t);
+        len -= t;
+    }
+}
+
+// Output rows per work item: aim for >= ~8 waves per CU.
+int default_rows(int64_t planes, int64_t h, int64_t w, int C, int T, int ncu) {
+    const int64_t strips = strip_count((int)w, C, T);
+    const int64_t target = (int64_t)ncu * 8;
+    int64_t per_col = std::max<int64_t>(1, target / std::max<int64_t>(1, strips * planes));
+    int64_t R = (h + per_col - 1) / per_col;
+    R = std::max<int64_t>(R, 4 * (int64_t)T);
+    R = std::min<int64_t>(R, 256);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(R, h));
+}
+
+// ---------------------------------------------------------------------------
+// cached launch plans: device-side work tables, counters and hipGraphs
+// ---------------------------------------------------------------------------
+struct PlanEntry {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<void*> owned;   // device buffers owned by this entry
+    std::shared_ptr<void> data;  // host-side description of `owned`
+    uint64_t last_use = 0;
+    ~PlanEntry() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (void* p : owned) (void)hipFree(p);
+    }
+};
+
+std::mutex g_plan_mu;
+std::map<std::string, std::unique_ptr<PlanEntry>> g_plans;
+std::map<int, hipStream_t> g_capture_stream;
+uint64_t g_use_clock = 0;
+constexpr size_t kMaxPlans = 64;
+
+int capture_stream(int dev, hipStream_t* out) {
+    auto it = g_capture_stream.find(dev);
+    if (it != g_capture_stream.end()) {
+        *out = it->second;
+        return WMC_OK;
+    }
+    hipStream_t s = nullptr;
+    WMC_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    g_capture_stream[dev] = s;
+    *out = s;
+    return WMC_OK;
+}
+
+void evict_plans() {
+    while (g_plans.size() > kMaxPlans) {
+        auto oldest = g_plans.begin();
+        for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
+            if (it->second->last_use < oldest->second->last_use) oldest = it;
+        g_plans.erase(oldest);
+    }
+}
+
+// Enqueue function: (stream, entry) -> status.  With use_graph the sequence
+// is recorded once per key on a private capture stream and replayed on st;
+// without, it is enqueued on st directly (the entry still owns its tables).
+// `prepare` runs once when the entry is created (uploads work tables).
+template <class Prep, class Enq>
+int run_plan(const std::string& key, int dev, hipStream_t st, bool use_graph, Prep&& prepare,
+             Enq&& enqueue) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    const std::string full = (use_graph ? "G|" : "D|") + key;
+    auto it = g_plans.find(full);
+    if (it == g_plans.end()) {
+        auto e = std::make_unique<PlanEntry>();
+        int rc = prepare(*e);
+        if (rc) return rc;
+        if (use_graph) {
+            if (injected("graph")) return fail(WMC_EHIP, "injected graph failure (WMC_FAULT_INJECT)");
+            hipStream_t cs;
+            rc = capture_stream(dev, &cs);
+            if (rc) return rc;
+            WMC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal),
+                    "hipStreamBeginCapture");
+            const int erc = enqueue(cs, *e);
+            hipGraph_t g = nullptr;
+            const hipError_t ce = hipStreamEndCapture(cs, &g);
+            if (erc) {
+                if (g) (void)hipGraphDestroy(g);
+                return erc;
+            }
+            if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+            e->graph = g;
+            WMC_HIP(hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+        }
+        it = g_plans.emplace(full, std::move(e)).first;
+    }
+    PlanEntry& e = *it->second;
+    e.last_use = ++g_use_clock;
+    int rc = WMC_OK;
+    if (use_graph) {
+        const hipError_t le = hipGraphLaunch(e.exec, st);
+        if (le != hipSuccess) rc = hip_fail(le, "hipGraphLaunch");
+    } else {
+        rc = enqueue(st, e);
+    }
+    evict_plans();
+    return rc;
+}
+
+int device_alloc(PlanEntry& e, size_t bytes, void** out) {
+    if (injected("alloc")) return fail(WMC_EHIP, "injected allocation failure (WMC_FAULT_INJECT)");
+    void* p = nullptr;
+    WMC_HIP(hipMalloc(&p, bytes < 256 ? 256 : bytes), "hipMalloc");
+    e.owned.push_back(p);
+    *out = p;
+    return WMC_OK;
+}
+
+template <class T>
+void key_add(std::string& k, const T& v) {
+    k.append(reinterpret_cast<const char*>(&v), sizeof(T));
+}
+
+// ---------------------------------------------------------------------------
+// tuning
+// ---------------------------------------------------------------------------
+struct Tuned {
+    int C, T, R;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, Tuned> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_path() {
+    if (const char* p = std::getenv("WMC_TUNE_CACHE")) return p;
+    const char* home = std::getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/wmc/tune.json";
+}
+
+// The cache file is a flat JSON object {"key": [C, T, R], ...}.
+void load_tune_file() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    std::ifstream in(tune_path());
+    if (!in) return;
+    std::stringstream ss;
+    ss << in.rdbuf();
+    const std::string txt = ss.str();
+    size_t pos = 0;
+    while (true) {
+        const size_t q0 = txt.find('"', pos);
+        if (q0 == std::string::npos) break;
+        const size_t q1 = txt.find('"', q0 + 1);
+        if (q1 == std::string::npos) break;
+        const std::string key = txt.substr(q0 + 1, q1 - q0 - 1);
+        const size_t b0 = txt.find('[', q1);
+        if (b0 == std::string::npos) break;
+        const size_t b1 = txt.find(']', b0);
+        if (b1 == std::string::npos) break;
+        int C = 0, T = 0, R = 0;
+        if (std::sscanf(txt.c_str() + b0 + 1, "%d , %d , %d", &C, &T, &R) == 3 &&
+            (C == 1 || C == 2 || C == 4) && valid_T(T) && R >= 1)
+            g_tune[key] = {C, T, R};
+        pos = b1 + 1;
+    }
+}
+
+void save_tune_file() {
+    const std::string path = tune_path();
+    for (size_t i = 1; i < path.size(); ++i)
+        if (path[i] == '/') (void)mkdir(path.substr(0, i).c_str(), 0755);
+    std::ofstream out(path + ".tmp");
+    if (!out) return;
+    out << "{\n";
+    size_t i = 0;
+    for (auto& kv : g_tune)
+        out << "  \"" << kv.first << "\": [" << kv.second.C << ", " << kv.second.T << ", "
+            << kv.second.R << "]" << (++i < g_tune.size() ? "," : "") << "\n";
+    out << "}\n";
+    out.close();
+    (void)std::rename((path + ".tmp").c_str(), path.c_str());
+}
+
+int ilog2_ceil(int64_t v) {
+    int r = 0;
+    while (((int64_t)1 << r) < v) ++r;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// batches (also used for single plane sets by the tuner)
+// ---------------------------------------------------------------------------
+struct BatchImg {
+    const float* src;  // u0 or f
+    const float* f;
+    float* out;
+    float* tmp;        // ping-pong partner in the workspace
+    int64_t h, w, ld, ps;
+    int channels;
+    int lam_index;
+    int lam_stride;
+};
+
+int64_t img_extent(const BatchImg& b) { return (b.channels - 1) * b.ps + (b.h - 1) * b.ld + b.w; }
+
+// Work table for one launch depth T: descriptors with strip/segment counts and
+// item bases.  Returns the number of work items.
+int64_t build_table(const std::vector<BatchImg>& imgs, int C, int T, int R,
+                    std::vector<ImageDesc>& tab) {
+    tab.clear();
+    int64_t base = 0;
+    for (const BatchImg& b : imgs) {
+        ImageDesc d{};
+        d.src0 = b.src;
+        d.f = b.f;
+        d.bufA = b.out;
+        d.bufB = b.tmp;
+        d.amap = nullptr;
+        d.ld = b.ld;
+        d.ps = b.ps;
+        d.H = (int32_t)b.h;
+        d.W = (int32_t)b.w;
+        d.channels = b.channels;
+        d.lam_index = b.lam_index;
+        d.lam_stride = b.lam_stride;
+        d.nstrip = strip_count((int)b.w, C, T);
+        d.nseg = seg_count((int)b.h, R);
+        d.vec = vec_cols({b.src, b.f, b.out, b.tmp}, b.ld, b.channels > 1 ? b.ps : 0) >= C ? 1 : 0;
+        d.item_base = base;
+        base += (int64_t)d.channels * d.nseg * d.nstrip;
+        tab.push_back(d);
+    }
+    return base;
+}
+
+// Launch sequence of a batched solve: depth of each launch and its buffers.
+struct Launch {
+    int T;
+    int src_sel, dst_sel;
+};
+
+std::vector<Launch> batch_schedule(int iters, int T) {
+    std::vector<int> depths;
+    split_run(iters, T, depths);
+    const int L = (int)depths.size();
+    std::vector<Launch> out;
+    for (int l = 0; l < L; ++l) {
+        const int dst = ((L - 1 - l) % 2 == 0) ? 1 : 2;  // the last launch writes out (A)
+        const int src = l == 0 ? 0 : out.back().dst_sel;
+        out.push_back({depths[l], src, dst});
+    }
+    return out;
+}
+
+// Persistent grid for (C, T, mode).
+int persistent_blocks(int dev, int C, int T, int mode, int64_t items) {
+    int per_cu = stream_blocks_per_cu(C, T, mode);
+    if (per_cu <= 0) per_cu = 1;
+    int64_t g = (int64_t)num_cu(dev) * per_cu;
+    const int64_t need = (items + 3) / 4;
+    if (g > need) g = need;
+    return (int)std::max<int64_t>(1, g);
+}
+
+// Enqueues (does not capture) a batched solve with explicit (C, T, R).
+// tables[T'] must hold device copies of the work tables for each depth used.
+int enqueue_batched(const std::vector<Launch>& sched, const std::map<int, ImageDesc*>& dtab,
+                    const std::map<int, int64_t>& items, int nimg, int C, int R, int mode,
+                    const float* lam, float dt, uint32_t* counters, int dev, hipStream_t st) {
+    hipError_t e = launch_fill_u32(counters, (int64_t)sched.size(), 0u, st);
+    if (e != hipSuccess) return hip_fail(e, "counter reset");
+    for (size_t l = 0; l < sched.size(); ++l) {
+        const Launch& L = sched[l];
+        LaunchArgs a{lam, dt, L.src_sel, L.dst_sel, R};
+        const int64_t n = items.at(L.T);
+        const int grid = persistent_blocks(dev, C, L.T, mode, n);
+        e = launch_stream_batched(C, L.T, mode, dtab.at(L.T), nimg, n, a, counters + l, grid, st);
+        if (e != hipSuccess) return hip_fail(e, "launch of the persistent kernel");
+    }
+    return WMC_OK;
+}
+
+// Device-side work tables of one batched plan.
+struct BatchTables {
+    std::map<int, ImageDesc*> dtab;  // per launch depth
+    std::map<int, int64_t> items;
+    uint32_t* counters = nullptr;
+};
+
+// Full batched solve with a fixed tuning.
+int batched_run(const std::vector<BatchImg>& imgs, const float* lam, int iters, float dt,
+                int mode, int C, int T, int R, bool use_graph, int dev, hipStream_t st) {
+    const std::vector<Launch> sched = batch_schedule(iters, T);
+    std::string key = "batched|";
+    key_add(key, C);
+    key_add(key, T);
+    key_add(key, R);
+    key_add(key, mode);
+    key_add(key, iters);
+    key_add(key, dt);
+    key_add(key, lam);
+    key_add(key, dev);
+    for (const BatchImg& b : imgs) key_add(key, b);
+    auto prepare = [&](PlanEntry& e) -> int {
+        auto t = std::make_shared<BatchTables>();
+        for (const Launch& L : sched) {
+            if (t->dtab.count(L.T)) continue;
+            std::vector<ImageDesc> tab;
+            const int64_t n = build_table(imgs, C, L.T, R, tab);
+            void* p = nullptr;
+            int rc = device_alloc(e, sizeof(ImageDesc) * tab.size(), &p);
+            if (rc) return rc;
+            WMC_HIP(hipMemcpy(p, tab.data(), sizeof(ImageDesc) * tab.size(), hipMemcpyHostToDevice),
+                    "hipMemcpy (work table)");
+            t->dtab[L.T] = static_cast<ImageDesc*>(p);
+            t->items[L.T] = n;
+        }
+        void* c = nullptr;
+        int rc = device_alloc(e, sizeof(uint32_t) * std::max<size_t>(1, sched.size()), &c);
+        if (rc) return rc;
+        t->counters = static_cast<uint32_t*>(c);
+        e.data = t;
+        return WMC_OK;
+    };
+    auto enqueue = [&](hipStream_t s, PlanEntry& e) -> int {
+        const BatchTables& t = *static_cast<const BatchTables*>(e.data.get());
+        return enqueue_batched(sched, t.dtab, t.items, (int)imgs.size(), C, R, mode, lam, dt,
+                               t.counters, dev, s);
+    };
+    return run_plan(key, dev, st, use_graph, prepare, enqueue);
+}
+
+// ---------------------------------------------------------------------------
+// single plane-set solve: schedule with checkpoints
+// ---------------------------------------------------------------------------
+struct SLaunch {
+    int T;
+    const float* src;
+    float* dst;
+};
+
+std::vector<SLaunch> solve_schedule(int iters, int T, int ckpt_every, const float* src0,
+                                    float* u_out, float* ws, float* ckpt, int64_t set_stride) {
+    std::vector<int> depth;
+    std::vector<int> end_t;
+    int t = 0;
+    while (t < iters) {
+        int stop = iters;
+        if (ckpt && ckpt_every > 0) stop = std::min(iters, (t / ckpt_every + 1) * ckpt_every);
+        std::vector<int> parts;
+        split_run(stop - t, T, parts);
+        for (int d : parts) {
+            t += d;
+            depth.push_back(d);
+            end_t.push_back(t);
+        }
+    }
+    const int L = (int)depth.size();
+    std::vector<SLaunch> out(L);
+    for (int l = L - 1; l >= 0; --l) {
+        float* dst;
+        if (l == L - 1) dst = u_out;
+        else if (ckpt && end_t[l] % ckpt_every == 0)
+            dst = ckpt + (int64_t)(end_t[l] / ckpt_every) * set_stride;
+        else
+            dst = (out[l + 1].dst == u_out) ? ws : u_out;
+        out[l].dst = dst;
+        out[l].T = depth[l];
+    }
+    for (int l = 0; l < L; ++l) out[l].src = l == 0 ? src0 : out[l - 1].dst;
+    return out;
+}
+
+int enqueue_single(const wmc_shape& s, const float* src, const float* f, float* dst,
+                   const float* lam, float dt, int C, int T, int R, hipStream_t st) {
+    const int mode = f ? kModeData : kModeFlow;
+    const bool vec = vec_cols({src, f, dst}, s.ld, s.n > 1 ? s.ps : 0) >= C;
+    ImageDesc d{};
+    d.src0 = src;
+    d.f = f;
+    d.bufA = dst;
+    d.bufB = dst;
+    d.ld = s.ld;
+    d.ps = s.ps;
+    d.H = (int32_t)s.h;
+    d.W = (int32_t)s.w;
+    d.channels = (int32_t)s.n;
+    d.lam_index = 0;
+    d.lam_stride = 1;
+    d.nstrip = strip_count((int)s.w, C, T);
+    d.nseg = seg_count((int)s.h, R);
+    d.vec = vec ? 1 : 0;
+    LaunchArgs a{lam, dt, 0, 1, R};
+    const hipError_t e = launch_stream_single(C, T, mode, false, d, a, st);
+    if (e != hipSuccess) return hip_fail(e, "launch of the streaming kernel");
+    return WMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+// Times `run(C, T, R, stream)` (one launch of T sweeps) for every candidate and
+// returns the fastest per sweep.  Synchronises st.
+template <class Run>
+int tune_search(Run&& run, int64_t h_max, hipStream_t st, Tuned* best_out) {
+    hipEvent_t e0, e1;
+    WMC_HIP(hipEventCreate(&e0), "hipEventCreate");
+    WMC_HIP(hipEventCreate(&e1), "hipEventCreate");
+    double best = 1e30;
+    Tuned best_t{2, 4, 64};
+    int rc = WMC_OK;
+    for (int C : {1, 2, 4})
+        for (int T : {1, 2, 3, 4, 6, 8})
+            for (int R : {16, 32, 64, 128}) {
+                if (R < 2 * T && R < h_max) continue;
+                if (R > 2 * h_max && R != 16) continue;
+                // warm up once, then take the best of three
+                rc = run(C, T, R, st);
+                if (rc) goto done;
+                {
+                    float ms_best = 1e30f;
+                    for (int rep = 0; rep < 3; ++rep) {
+                        WMC_HIP(hipEventRecord(e0, st), "hipEventRecord");
+                        rc = run(C, T, R, st);
+                        if (rc) goto done;
+                        WMC_HIP(hipEventRecord(e1, st), "hipEventRecord");
+                        WMC_HIP(hipEventSynchronize(e1), "hipEventSynchronize");
+                        float ms = 0.0f;
+                        WMC_HIP(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                        ms_best = std::min(ms_best, ms);
+                    }
+                    const double per_sweep = ms_best / T;
+                    if (per_sweep < best) {
+                        best = per_sweep;
+                        best_t = {C, T, R};
+                    }
+                }
+            }
+done:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *best_out = best_t;
+    return WMC_OK;
+}
+
+enum class TuneMode { Off, Cached, Force, Auto };
+
+TuneMode tune_mode() {
+    const char* v = std::getenv("WMC_TUNE");
+    if (!v) return TuneMode::Auto;
+    if (!std::strcmp(v, "off")) return TuneMode::Off;
+    if (!std::strcmp(v, "cached")) return TuneMode::Cached;
+    if (!std::strcmp(v, "force")) return TuneMode::Force;
+    return TuneMode::Auto;
+}
+
+std::string arch_name(int dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// Looks up / searches a tuning.  `search` fills *t; `deflt` is the fallback.
+template <class Search>
+int get_tuning(const std::string& key, Tuned deflt, Search&& search, Tuned* t) {
+    const TuneMode m = tune_mode();
+    if (m == TuneMode::Off) {
+        *t = deflt;
+        return WMC_OK;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_file();
+        auto it = g_tune.find(key);
+        if (m != TuneMode::Force && it != g_tune.end()) {
+            *t = it->second;
+            return WMC_OK;
+        }
+    }
+    if (m == TuneMode::Cached) {
+        *t = deflt;
+        return WMC_OK;
+    }
+    Tuned found = deflt;
+    int rc = search(&found);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = found;
+    save_tune_file();
+    *t = found;
+    return WMC_OK;
+}
+
+std::string single_tune_key(int dev, const wmc_shape& s, int mode) {
+    std::ostringstream k;
+    k << arch_name(dev) << "|single|" << (mode == kModeData ? "data" : "flow") << "|h" << ilog2_ceil(s.h)
+      << "|w" << ilog2_ceil(s.w) << "|n" << ilog2_ceil(s.n);
+    return k.str();
+}
+
+int tune_single(int dev, const wmc_shape& s, const float* src, const float* f, const float* lam,
+                float dt, float* ws, hipStream_t st, Tuned* t) {
+    const int mode = f ? kModeData : kModeFlow;
+    const int C0 = std::min(2, vec_cols({src, f, ws}, s.ld, s.n > 1 ? s.ps : 0));
+    const Tuned deflt{C0, 4, default_rows(s.n, s.h, s.w, C0, 4, num_cu(dev))};
+    auto search = [&](Tuned* out) {
+        auto run = [&](int C, int T, int R, hipStream_t ss) {
+            return enqueue_single(s, src, f, ws, lam, dt, C, T, R, ss);
+        };
+        return tune_search(run, s.h, st, out);
+    };
+    return get_tuning(single_tune_key(dev, s, mode), deflt, search, t);
+}
+
+std::string batch_tune_key(int dev, const std::vector<BatchImg>& imgs, int mode) {
+    int64_t px = 0;
+    std::vector<int64_t> ws;
+    for (const BatchImg& b : imgs) {
+        px += b.h * b.w * b.channels;
+        ws.push_back(b.w);
+    }
+    std::sort(ws.begin(), ws.end());
+    std::ostringstream k;
+    k << arch_name(dev) << "|batch|" << (mode == kModeData ? "data" : "flow") << "|px" << ilog2_ceil(px)
+      << "|wmed" << ilog2_ceil(ws[ws.size() / 2]) << "|imgs" << ilog2_ceil((int64_t)imgs.size());
+    return k.str();
+}
+
+int tune_batch(int dev, const std::vector<BatchImg>& imgs, const float* lam, float dt, int mode,
+               hipStream_t st, Tuned* t) {
+    int64_t hmax = 1;
+    for (const BatchImg& b : imgs) hmax = std::max(hmax, b.h);
+    const Tuned deflt{2, 4, 32};
+    auto search = [&](Tuned* out) {
+        // one launch of T sweeps reading the inputs and writing the workspace
+        auto run = [&](int C, int T, int R, hipStream_t ss) {
+            std::vector<Launch> one{{T, 0, 2}};
+            std::vector<ImageDesc> tab;
+            const int64_t n = build_table(imgs, C, T, R, tab);
+            std::string key = "tune|";
+            key_add(key, C);
+            key_add(key, T);
+            key_add(key, R);
+            key_add(key, mode);
+            key_add(key, dev);
+            for (const BatchImg& b : imgs) key_add(key, b);
+            auto prepare = [&](PlanEntry& e) -> int {
+                auto tb = std::make_shared<BatchTables>();
+                void* p = nullptr;
+                int rc = device_alloc(e, sizeof(ImageDesc) * tab.size(), &p);
+                if (rc) return rc;
+                WMC_HIP(hipMemcpy(p, tab.data(), sizeof(ImageDesc) * tab.size(),
+                                  hipMemcpyHostToDevice),
+                        "hipMemcpy (work table)");
+                tb->dtab[T] = static_cast<ImageDesc*>(p);
+                tb->items[T] = n;
+                void* c = nullptr;
+                rc = device_alloc(e, sizeof(uint32_t), &c);
+                if (rc) return rc;
+                tb->counters = static_cast<uint32_t*>(c);
+                e.data = tb;
+                return WMC_OK;
+            };
+            auto enqueue = [&](hipStream_t s2, PlanEntry& e) -> int {
+                const BatchTables& tb = *static_cast<const BatchTables*>(e.data.get());
+                return enqueue_batched(one, tb.dtab, tb.items, (int)imgs.size(), C, R, mode, lam,
+                                       dt, tb.counters, dev, s2);
+            };
+            return run_plan(key, dev, ss, false, prepare, enqueue);
+        };
+        return tune_search(run, hmax, st, out);
+    };
+    return get_tuning(batch_tune_key(dev, imgs, mode), deflt, search, t);
+}
+
+int resolve_tuning(const wmc_tuning* tune, Tuned auto_t, Tuned* t, bool* graph) {
+    *t = auto_t;
+    *graph = true;
+    if (!tune) return WMC_OK;
+    if (tune->cols) {
+        if (tune->cols != 1 && tune->cols != 2 && tune->cols != 4)
+            return fail(WMC_EINVAL, "tuning: cols must be 1, 2 or 4");
+        t->C = tune->cols;
+    }
+    if (tune->tsteps) {
+        if (!valid_T(tune->tsteps)) return fail(WMC_EINVAL, "tuning: tsteps must be 1, 2, 3, 4, 6 or 8");
+        t->T = tune->tsteps;
+    }
+    if (tune->seg_rows) {
+        if (tune->seg_rows < 1) return fail(WMC_EINVAL, "tuning: seg_rows must be >= 1");
+        t->R = tune->seg_rows;
+    }
+    *graph = tune->use_graph != 0;
+    return WMC_OK;
+}
+
+bool tuning_complete(const wmc_tuning* tune) {
+    return tune && tune->cols && tune->tsteps && tune->seg_rows;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* wmc_last_error(void) { return g_err.c_str(); }
+
+size_t wmc_solve_workspace(wmc_shape s) {
+    if (check_shape(s)) return 0;
+    return (size_t)set_stride_elems(s) * sizeof(float);
+}
+
+int64_t wmc_set_stride(wmc_shape s) {
+    if (check_shape(s)) return 0;
+    return set_stride_elems(s);
+}
+
+int64_t wmc_num_checkpoints(int iters, int ckpt_every) {
+    if (iters <= 0 || ckpt_every <= 0) return 0;
+    return (iters + ckpt_every - 1) / ckpt_every;
+}
+
+int wmc_compute(const float* u, float* hw, wmc_shape s, void* stream) {
+    g_err.clear();
+    int rc = check_shape(s);
+    if (rc) return rc;
+    if (!u || !hw) return fail(WMC_EINVAL, "wmc_compute: null pointer");
+    const int64_t ext = extent_elems(s);
+    if (overlaps(range_of(u, ext, 4), range_of(hw, ext, 4)))
+        return fail(WMC_EINVAL, "wmc_compute: output overlaps input");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    const int C = vec_cols({u, hw}, s.ld, s.n > 1 ? s.ps : 0);
+    const int R = default_rows(s.n, s.h, s.w, C, 1, num_cu(dev));
+    ImageDesc d{};
+    d.src0 = u;
+    d.bufA = hw;
+    d.bufB = hw;
+    d.ld = s.ld;
+    d.ps = s.ps;
+    d.H = (int32_t)s.h;
+    d.W = (int32_t)s.w;
+    d.channels = (int32_t)s.n;
+    d.lam_stride = 1;
+    d.nstrip = strip_count((int)s.w, C, 1);
+    d.nseg = seg_count((int)s.h, R);
+    d.vec = 1;
+    LaunchArgs a{nullptr, 0.0f, 0, 1, R};
+    const hipError_t e = launch_stream_single(C, 1, kModeCompute, false, d, a, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "wmc_compute launch");
+    return WMC_OK;
+}
+
+int wmc_step(const float* u, const float* f, float* u_out, const float* lam, float dt,
+             uint8_t* argmin_out, wmc_shape s, void* stream) {
+    g_err.clear();
+    int rc = check_shape(s);
+    if (rc) return rc;
+    if (!u || !u_out) return fail(WMC_EINVAL, "wmc_step: null u or u_out");
+    if (f && !lam) return fail(WMC_EINVAL, "wmc_step: lam is required with a data term");
+    if (!std::isfinite(dt)) return fail(WMC_EINVAL, "wmc_step: dt must be finite");
+    const int64_t ext = extent_elems(s);
+    const Range ro = range_of(u_out, ext, 4);
+    if (overlaps(ro, range_of(u, ext, 4)) || overlaps(ro, range_of(f, ext, 4)) ||
+        overlaps(ro, range_of(argmin_out, ext, 1)))
+        return fail(WMC_EINVAL, "wmc_step: u_out overlaps an input (updates are synchronous)");
+    if (argmin_out && (overlaps(range_of(argmin_out, ext, 1), range_of(u, ext, 4)) ||
+                       overlaps(range_of(argmin_out, ext, 1), range_of(f, ext, 4))))
+        return fail(WMC_EINVAL, "wmc_step: argmin_out overlaps an input");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    const int mode = f ? kModeData : kModeFlow;
+    const int C = vec_cols({u, f, u_out}, s.ld, s.n > 1 ? s.ps : 0);
+    const int R = default_rows(s.n, s.h, s.w, C, 1, num_cu(dev));
+    ImageDesc d{};
+    d.src0 = u;
+    d.f = f;
+    d.bufA = u_out;
+    d.bufB = u_out;
+    d.amap = argmin_out;
+    d.ld = s.ld;
+    d.ps = s.ps;
+    d.H = (int32_t)s.h;
+    d.W = (int32_t)s.w;
+    d.channels = (int32_t)s.n;
+    d.lam_stride = 1;
+    d.nstrip = strip_count((int)s.w, C, 1);
+    d.nseg = seg_count((int)s.h, R);
+    d.vec = 1;
+    LaunchArgs a{lam, dt, 0, 1, R};
+    const hipError_t e =
+        launch_stream_single(C, 1, mode, argmin_out != nullptr, d, a, as_stream(stream));
+    if (e != hipSuccess) return hip_fail(e, "wmc_step launch");
+    return WMC_OK;
+}
+
+int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, int iters,
+              float dt, float* ckpt, int ckpt_every, const wmc_tuning* tune, void* ws,
+              size_t ws_bytes, wmc_shape s, void* stream) {
+    g_err.clear();
+    int rc = check_shape(s);
+    if (rc) return rc;
+    if (!u_out) return fail(WMC_EINVAL, "wmc_solve: null u_out");
+    if (!f && !u0) return fail(WMC_EINVAL, "wmc_solve: the curvature flow (f == NULL) needs u0");
+    if (f && !lam) return fail(WMC_EINVAL, "wmc_solve: lam is required with a data term");
+    if (iters < 0) return fail(WMC_EINVAL, "wmc_solve: iters must be >= 0");
+    if (!std::isfinite(dt)) return fail(WMC_EINVAL, "wmc_solve: dt must be finite");
+    if (ckpt && ckpt_every < 1) return fail(WMC_EINVAL, "wmc_solve: ckpt_every must be >= 1");
+    const int64_t ext = extent_elems(s);
+    const int64_t stride = set_stride_elems(s);
+    const size_t need = wmc_solve_workspace(s);
+    if (iters >= 2 && (!ws || ws_bytes < need))
+        return fail(WMC_ENOMEM, "wmc_solve: workspace smaller than wmc_solve_workspace()");
+    const float* src0 = u0 ? u0 : f;
+    const int64_t nck = ckpt ? wmc_num_checkpoints(iters, ckpt_every) : 0;
+    const Range ro = range_of(u_out, ext, 4), rs = range_of(src0, ext, 4), rf = range_of(f, ext, 4);
+    const Range rw = range_of(iters >= 2 ? ws : nullptr, ext, 4);
+    const Range rc_ = range_of(nck ? ckpt : nullptr, (nck - 1) * stride + ext, 4);
+    if (overlaps(ro, rs) || overlaps(ro, rf) || overlaps(ro, rw) || overlaps(ro, rc_))
+        return fail(WMC_EINVAL, "wmc_solve: u_out overlaps an input, ckpt or ws");
+    if (overlaps(rw, rs) || overlaps(rw, rf) || overlaps(rw, rc_) || overlaps(rc_, rs) ||
+        overlaps(rc_, rf))
+        return fail(WMC_EINVAL, "wmc_solve: ws / ckpt overlap the inputs or each other");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t st = as_stream(stream);
+    if (iters == 0) {
+        const hipError_t e = launch_copy_planes(src0, u_out, s.n, s.h, s.w, s.ld, s.ps, st);
+        return e == hipSuccess ? WMC_OK : hip_fail(e, "copy");
+    }
+    const int mode = f ? kModeData : kModeFlow;
+    Tuned t{};
+    bool graph = true;
+    if (tuning_complete(tune)) {
+        rc = resolve_tuning(tune, Tuned{2, 4, 64}, &t, &graph);
+    } else {
+        Tuned auto_t{};
+        rc = tune_single(dev, s, src0, f, lam, dt, iters >= 2 ? static_cast<float*>(ws) : u_out, st,
+                         &auto_t);
+        if (rc) return rc;
+        rc = resolve_tuning(tune, auto_t, &t, &graph);
+    }
+    if (rc) return rc;
+    (void)mode;
+    const std::vector<SLaunch> sched =
+        solve_schedule(iters, t.T, ckpt ? ckpt_every : 0, src0, u_out, static_cast<float*>(ws),
+                       nck ? ckpt : nullptr, stride);
+    auto enqueue = [&](hipStream_t ss, PlanEntry&) -> int {
+        if (nck) {
+            const hipError_t e = launch_copy_planes(src0, ckpt, s.n, s.h, s.w, s.ld, s.ps, ss);
+            if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+        }
+        for (const SLaunch& L : sched) {
+            const int r = enqueue_single(s, L.src, f, L.dst, lam, dt, t.C, L.T, t.R, ss);
+            if (r) return r;
+        }
+        return WMC_OK;
+    };
+    if (!graph) {
+        PlanEntry scratch;
+        return enqueue(st, scratch);
+    }
+    std::string key = "solve|";
+    key_add(key, s);
+    key_add(key, f);
+    key_add(key, u0);
+    key_add(key, u_out);
+    key_add(key, lam);
+    key_add(key, iters);
+    key_add(key, dt);
+    key_add(key, ckpt);
+    key_add(key, ckpt_every);
+    key_add(key, ws);
+    key_add(key, t);
+    key_add(key, dev);
+    auto prepare = [](PlanEntry&) { return WMC_OK; };
+    return run_plan(key, dev, st, true, prepare, enqueue);
+}
+
+size_t wmc_batched_workspace(const wmc_image* imgs, int n_imgs) {
+    if (!imgs || n_imgs <= 0) return 0;
+    size_t total = 0;
+    for (int i = 0; i < n_imgs; ++i) {
+        const wmc_image& m = imgs[i];
+        if (m.channels < 1 || m.h < 1 || m.w < 1 || m.ld < m.w) return 0;
+        const int64_t ext = (int64_t)(m.channels - 1) * m.ps + (m.h - 1) * m.ld + m.w;
+        total += (size_t)((ext + 63) / 64 * 64) * sizeof(float);
+    }
+    return total;
+}
+
+int wmc_solve_batched(const wmc_image* imgs, int n_imgs, const float* lam, int iters, float dt,
+                      const wmc_tuning* tune, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (!imgs || n_imgs < 1) return fail(WMC_EINVAL, "wmc_solve_batched: no images");
+    if (iters < 0) return fail(WMC_EINVAL, "wmc_solve_batched: iters must be >= 0");
+    if (!std::isfinite(dt)) return fail(WMC_EINVAL, "wmc_solve_batched: dt must be finite");
+    const bool data = imgs[0].f != nullptr;
+    std::vector<BatchImg> b(n_imgs);
+    std::vector<Range> outs(n_imgs), ins;
+    size_t off = 0;
+    for (int i = 0; i < n_imgs; ++i) {
+        const wmc_image& m = imgs[i];
+        wmc_shape s{m.channels, m.h, m.w, m.ld, m.ps};
+        int rc = check_shape(s);
+        if (rc) return fail(rc, "wmc_solve_batched: image " + std::to_string(i) + ": " + g_err);
+        if (!m.out) return fail(WMC_EINVAL, "wmc_solve_batched: null out");
+        if ((m.f != nullptr) != data)
+            return fail(WMC_EINVAL, "wmc_solve_batched: all images must have a data term or none");
+        if (!m.f && !m.u0) return fail(WMC_EINVAL, "wmc_solve_batched: flow images need u0");
+        if (data && m.lam_index < 0) return fail(WMC_EINVAL, "wmc_solve_batched: lam_index < 0");
+        const int64_t ext = extent_elems(s);
+        outs[i] = range_of(m.out, ext, 4);
+        ins.push_back(range_of(m.u0, ext, 4));
+        ins.push_back(range_of(m.f, ext, 4));
+        b[i] = BatchImg{m.u0 ? m.u0 : m.f, m.f, m.out,
+                        static_cast<float*>(ws) ? reinterpret_cast<float*>(static_cast<char*>(ws) + off)
+                                                : nullptr,
+                        m.h, m.w, m.ld, m.ps, m.channels, m.lam_index, 0};
+        off += (size_t)((ext + 63) / 64 * 64) * sizeof(float);
+    }
+    if (data && !lam) return fail(WMC_EINVAL, "wmc_solve_batched: lam is required with a data term");
+    if (iters >= 2 && (!ws || ws_bytes < off))
+        return fail(WMC_ENOMEM, "wmc_solve_batched: workspace smaller than wmc_batched_workspace()");
+    const Range rw = range_of(iters >= 2 ? ws : nullptr, (int64_t)off, 1);
+    for (int i = 0; i < n_imgs; ++i) {
+        if (overlaps(outs[i], rw)) return fail(WMC_EINVAL, "wmc_solve_batched: out overlaps ws");
+        for (const Range& r : ins)
+            if (overlaps(outs[i], r)) return fail(WMC_EINVAL, "wmc_solve_batched: out overlaps an input");
+        for (int j = i + 1; j < n_imgs; ++j)
+            if (overlaps(outs[i], outs[j])) return fail(WMC_EINVAL, "wmc_solve_batched: outputs overlap");
+    }
+    for (const Range& r : ins)
+        if (overlaps(rw, r)) return fail(WMC_EINVAL, "wmc_solve_batched: ws overlaps an input");
+    int dev;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t st = as_stream(stream);
+    if (iters == 0) {
+        for (int i = 0; i < n_imgs; ++i) {
+            const hipError_t e =
+                launch_copy_planes(b[i].src, b[i].out, b[i].channels, b[i].h, b[i].w, b[i].ld, b[i].ps, st);
+            if (e != hipSuccess) return hip_fail(e, "copy");
+        }
+        return WMC_OK;
+    }
+    const int mode = data ? kModeData : kModeFlow;
+    Tuned t{};
+    bool graph = true;
+    if (tuning_complete(tune)) {
+        rc = resolve_tuning(tune, Tuned{2, 4, 32}, &t, &graph);
+    } else {
+        Tuned auto_t{};
+        rc = tune_batch(dev, b, lam, dt, mode, st, &auto_t);
+        if (rc) return rc;
+        rc = resolve_tuning(tune, auto_t, &t, &graph);
+    }
+    if (rc) return rc;
+    return batched_run(b, lam, iters, dt, mode, t.C, t.T, t.R, graph, dev, st);
+}
+
+int wmc_autotune(const wmc_image* imgs, int n_imgs, int iters, wmc_tuning* out, void* ws,
+                 size_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (!imgs || n_imgs < 1 || !out) return fail(WMC_EINVAL, "wmc_autotune: bad arguments");
+    (void)iters;
+    const bool data = imgs[0].f != nullptr;
+    std::vector<BatchImg> b(n_imgs);
+    size_t off = 0;
+    for (int i = 0; i < n_imgs; ++i) {
+        const wmc_image& m = imgs[i];
+        wmc_shape s{m.channels, m.h, m.w, m.ld, m.ps};
+        int rc = check_shape(s);
+        if (rc) return rc;
+        if ((m.f != nullptr) != data || (!m.f && !m.u0) || !m.out)
+            return fail(WMC_EINVAL, "wmc_autotune: inconsistent image descriptors");
+        const int64_t ext = extent_elems(s);
+        b[i] = BatchImg{m.u0 ? m.u0 : m.f, m.f, m.out,
+                        reinterpret_cast<float*>(static_cast<char*>(ws) + off), m.h, m.w, m.ld, m.ps,
+                        m.channels, m.lam_index, 0};
+        off += (size_t)((ext + 63) / 64 * 64) * sizeof(float);
+    }
+    if (!ws || ws_bytes < off) return fail(WMC_ENOMEM, "wmc_autotune: workspace too small");
+    int dev;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    // lambda values only steer the arithmetic, not the timing: use a device zero
+    float* zl = nullptr;
+    WMC_HIP(hipMalloc(&zl, 256 * sizeof(float)), "hipMalloc");
+    hipStream_t st = as_stream(stream);
+    rc = WMC_OK;
+    if (launch_fill_f32(zl, 256, 1.0f, st) != hipSuccess) rc = fail(WMC_EHIP, "fill");
+    Tuned t{};
+    if (!rc) {
+        for (BatchImg& x : b) x.lam_index = 0;
+        rc = tune_batch(dev, b, zl, 0.0f, data ? kModeData : kModeFlow, st, &t);
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(zl);
+    if (rc) return rc;
+    out->cols = t.C;
+    out->tsteps = t.T;
+    out->seg_rows = t.R;
+    out->use_graph = 1;
+    return WMC_OK;
+}
+
+size_t wmc_backward_workspace(wmc_shape s, int iters, int ckpt_every) {
+    if (check_shape(s) || iters < 0 || ckpt_every < 1) return 0;
+    const size_t set = (size_t)set_stride_elems(s) * sizeof(float);
+    const int c = std::min(ckpt_every, std::max(iters, 1));
+    const size_t states = (size_t)std::max(c - 1, 0) * set;
+    const size_t grads = 2 * set;
+    const size_t sel = (size_t)(set_stride_elems(s) + 255) / 256 * 256;
+    const size_t part = (size_t)s.n * adj_blocks_per_plane(s.h, s.w) * sizeof(float);
+    return states + grads + sel + (part + 255) / 256 * 256;
+}
+
+int wmc_backward(const float* f, const float* u0, const float* lam, int iters, float dt,
+                 const float* ckpt, int ckpt_every, const float* g_out, float* g_f, float* g_u0,
+                 float* g_lam, void* ws, size_t ws_bytes, wmc_shape s, void* stream) {
+    g_err.clear();
+    int rc = check_shape(s);
+    if (rc) return rc;
+    if (!f && !u0) return fail(WMC_EINVAL, "wmc_backward: the curvature flow needs u0");
+    if (f && !lam) return fail(WMC_EINVAL, "wmc_backward: lam is required with a data term");
+    if (iters < 0 || ckpt_every < 1) return fail(WMC_EINVAL, "wmc_backward: bad iters / ckpt_every");
+    if (iters > 0 && !ckpt) return fail(WMC_EINVAL, "wmc_backward: checkpoints are required");
+    if (!g_out) return fail(WMC_EINVAL, "wmc_backward: null g_out");
+    if (!std::isfinite(dt)) return fail(WMC_EINVAL, "wmc_backward: dt must be finite");
+    const size_t need = wmc_backward_workspace(s, iters, ckpt_every);
+    if (!ws || ws_bytes < need) return fail(WMC_ENOMEM, "wmc_backward: workspace too small");
+    const int64_t ext = extent_elems(s);
+    const Range rw = range_of(ws, (int64_t)need, 1);
+    for (const void* p : {(const void*)g_f, (const void*)g_u0})
+        if (p && (overlaps(range_of(p, ext, 4), rw) || overlaps(range_of(p, ext, 4), range_of(g_out, ext, 4))))
+            return fail(WMC_EINVAL, "wmc_backward: outputs overlap the workspace or g_out");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t st = as_stream(stream);
+    const int64_t set = set_stride_elems(s);
+    char* w = static_cast<char*>(ws);
+    const int c = std::min(ckpt_every, std::max(iters, 1));
+    float* states = reinterpret_cast<float*>(w);
+    w += (size_t)std::max(c - 1, 0) * set * sizeof(float);
+    float* gA = reinterpret_cast<float*>(w);
+    w += set * sizeof(float);
+    float* gB = reinterpret_cast<float*>(w);
+    w += set * sizeof(float);
+    uint8_t* sel = reinterpret_cast<uint8_t*>(w);
+    w += (size_t)(set + 255) / 256 * 256;
+    float* part = reinterpret_cast<float*>(w);
+    const int nblk = adj_blocks_per_plane(s.h, s.w);
+    const bool data = f != nullptr;
+    const int mode = data ? kModeData : kModeFlow;
+    const int C1 = 1;
+    const int R1 = default_rows(s.n, s.h, s.w, C1, 1, num_cu(dev));
+    hipError_t e;
+    if (g_lam) {
+        e = launch_fill_f32(g_lam, s.n, 0.0f, st);
+        if (e != hipSuccess) return hip_fail(e, "fill");
+    }
+    if (data && g_f) {
+        e = launch_fill_f32(g_f, (s.n - 1) * s.ps + (s.h - 1) * s.ld + s.w, 0.0f, st);
+        if (e != hipSuccess) return hip_fail(e, "fill");
+    }
+    e = launch_copy_planes(g_out, gA, s.n, s.h, s.w, s.ld, s.ps, st);
+    if (e != hipSuccess) return hip_fail(e, "copy");
+    float* gcur = gA;
+    float* gnext = gB;
+    const int nseg = (int)wmc_num_checkpoints(iters, ckpt_every);
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int t0 = sg * ckpt_every;
+        const int t1 = std::min(t0 + ckpt_every, iters);
+        std::vector<const float*> st_ptr(t1 - t0);
+        st_ptr[0] = ckpt + (int64_t)sg * set;
+        for (int t = t0 + 1; t < t1; ++t) {
+            float* dst = states + (int64_t)(t - t0 - 1) * set;
+            rc = enqueue_single(s, st_ptr[t - t0 - 1], f, dst, lam, dt, C1, 1, R1, st);
+            if (rc) return rc;
+            st_ptr[t - t0] = dst;
+        }
+        for (int t = t1 - 1; t >= t0; --t) {
+            AdjArgs a{};
+            a.u = st_ptr[t - t0];
+            a.f = f;
+            a.g = gcur;
+            a.g_prev = gnext;
+            a.g_f = data ? g_f : nullptr;
+            a.sel = sel;
+            a.lam_part = part;
+            a.lam = lam;
+            a.dt = dt;
+            a.n = s.n;
+            a.h = s.h;
+            a.w = s.w;
+            a.ld = s.ld;
+            a.ps = s.ps;
+            e = launch_adjoint_step(a, st);
+            if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+            if (data && g_lam) {
+                e = launch_lambda_reduce(part, s.n, nblk, g_lam, st);
+                if (e != hipSuccess) return hip_fail(e, "lambda reduction");
+            }
+            std::swap(gcur, gnext);
+        }
+    }
+    (void)mode;
+    if (g_u0) {
+        e = launch_copy_planes(gcur, g_u0, s.n, s.h, s.w, s.ld, s.ps, st);
+        if (e != hipSuccess) return hip_fail(e, "copy");
+    }
+    if (data && g_f && !u0) {
+        e = launch_add_planes(gcur, g_f, s.n, s.h, s.w, s.ld, s.ps, st);
+        if (e != hipSuccess) return hip_fail(e, "accumulate");
+    }
+    return WMC_OK;
+}
+
+int wmc_selftest(void) {
+    g_err.clear();
+    int dev;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    int* d = nullptr;
+    WMC_HIP(hipMalloc(&d, 4 * sizeof(int)), "hipMalloc");
+    int h[4] = {0, 0, 0, 0};
+    hipError_t e = launch_selftest(d, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(h, d, sizeof h, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "selftest");
+    for (int i = 0; i < 4; ++i)
+        if (h[i] != 1) return fail(WMC_EHIP, "selftest: DPP wave shifts do not move data as assumed");
+    return WMC_OK;
+}
+
+void wmc_release(void) {
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        g_plans.clear();
+        for (auto& kv : g_capture_stream) (void)hipStreamDestroy(kv.second);
+        g_capture_stream.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    g_tune_loaded = false;
+}
+
+}  // extern "C"

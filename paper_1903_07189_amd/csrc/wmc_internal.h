@@ -1,0 +1,97 @@
+// wmc_internal.h -- declarations shared by the host side (wmc_api.cpp) and the
+// kernels (wmc_stream.hip, wmc_adjoint.hip) of libwmc.  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace wmc {
+
+// ---------------------------------------------------------------------------
+// Work decomposition of the streaming kernel.
+//
+// One wave processes one work item: a vertical strip of 64*C columns (C per
+// lane) of one plane, streamed top to bottom over a segment of R output
+// rows.  Inside the wave the rows of T consecutive Jacobi sweeps are kept in
+// registers as a pipeline (sweep k lags sweep k-1 by one row), so the wave
+// reads U and f once and writes U once per T sweeps.
+//
+// Strips overlap by a halo of round_up(T, C) columns on each side; strip j
+// loads columns [j*(64C - 2*halo), j*(64C - 2*halo) + 64C) and owns the
+// output columns between the halos.  The first strip starts at column 0 and
+// the last one reaches column W-1, where the image border is exact, so their
+// outer halos are output too.  Segments overlap by T rows (recomputed).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int halo_cols(int C, int T) { return ((T + C - 1) / C) * C; }
+
+__host__ __device__ inline int strip_count(int W, int C, int T) {
+    const int width = 64 * C, step = width - 2 * halo_cols(C, T);
+    if (W <= width) return 1;
+    return 1 + (W - width + step - 1) / step;
+}
+
+__host__ __device__ inline int seg_count(int H, int R) { return (H + R - 1) / R; }
+
+// One image (all its channels) as seen by the kernels.
+struct ImageDesc {
+    const float* src0;  // state read by a launch with src_sel == 0
+    const float* f;     // data term (null: curvature flow / compute)
+    float* bufA;        // selectable buffers (dst_sel/src_sel 1 and 2)
+    float* bufB;
+    uint8_t* amap;      // selection map (argmin variant only)
+    int64_t ld, ps;     // row / plane stride, elements
+    int32_t H, W;
+    int32_t channels;
+    int32_t lam_index;  // channel c uses lam[lam_index + c*lam_stride]
+    int32_t lam_stride;
+    int32_t nstrip, nseg;
+    int32_t vec;        // 1: every row start of every buffer is 4C-byte aligned
+    int64_t item_base;  // index of the image's first work item in the launch
+};
+
+struct LaunchArgs {
+    const float* lam;  // device lambda array (may be null in flow/compute mode)
+    float dt;          // > 0: step size, <= 0: default
+    int32_t src_sel;   // 0: src0, 1: bufA, 2: bufB
+    int32_t dst_sel;   // 1: bufA, 2: bufB
+    int32_t R;         // output rows per work item
+};
+
+enum { kModeCompute = 0, kModeData = 1, kModeFlow = 2 };
+
+// Host-side launchers (wmc_stream.hip).  Return a hipError_t.
+bool stream_variant_exists(int C, int T, int mode, bool argmin);
+hipError_t launch_stream_single(int C, int T, int mode, bool argmin, const ImageDesc& d,
+                                const LaunchArgs& a, hipStream_t st);
+hipError_t launch_stream_batched(int C, int T, int mode, const ImageDesc* dtable, int nimg,
+                                 int64_t total_items, const LaunchArgs& a, uint32_t* counter,
+                                 int grid_blocks, hipStream_t st);
+int stream_blocks_per_cu(int C, int T, int mode);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
+hipError_t launch_copy_planes(const float* src, float* dst, int64_t n, int64_t h, int64_t w,
+                              int64_t ld, int64_t ps, hipStream_t st);
+hipError_t launch_add_planes(const float* src, float* dst, int64_t n, int64_t h, int64_t w,
+                             int64_t ld, int64_t ps, hipStream_t st);
+hipError_t launch_selftest(int* out_flags, hipStream_t st);
+
+// Adjoint launchers (wmc_adjoint.hip).
+struct AdjArgs {
+    const float* u;     // U^t (plane set)
+    const float* f;     // data term or null (flow)
+    const float* g;     // dL/dU^{t+1}
+    float* g_prev;      // dL/dU^t (out)
+    float* g_f;         // dL/df accumulator (data mode) or null
+    uint8_t* sel;       // selection map scratch (1 byte per element, layout of u)
+    float* lam_part;    // per plane: partial sums of dL/dlam, nblk_per_plane each
+    const float* lam;
+    float dt;
+    int64_t n, h, w, ld, ps;
+};
+int adj_blocks_per_plane(int64_t h, int64_t w);
+hipError_t launch_adjoint_step(const AdjArgs& a, hipStream_t st);
+hipError_t launch_lambda_reduce(const float* lam_part, int64_t n, int nblk, float* g_lam,
+                                hipStream_t st);
+
+}  // namespace wmc

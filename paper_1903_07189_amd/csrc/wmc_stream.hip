@@ -1,0 +1,504 @@
+// wmc_stream.hip -- the streaming, temporally blocked WMC kernel for gfx950.
+//
+// One wave = one work item (a strip of 64*C columns of one plane and a
+// segment of output rows).  Each lane owns C adjacent columns.  The wave walks
+// down the rows; at row step n it
+//   1. takes input row n (prefetched three steps earlier) and forms its row
+//      quantities (a, s, q) with the horizontal neighbours fetched from the
+//      adjacent lanes by DPP wave shifts -- no LDS, no barriers;
+//   2. for k = 1..T computes row n-k of sweep k from the three most recent
+//      rows of sweep k-1 (held in registers) and forms that row's
+//      quantities for sweep k+1;
+//   3. writes row n-T of sweep T.
+// Image rows above 0 / below H-1 are the replicate border; segment ends that
+// are not image borders are covered by T extra rows of recomputation.  The
+// data term f is kept in a per-lane LDS ring of T+1 rows (written and read by
+// the same lane only).
+//
+// Sweeps are Jacobi (every pixel of sweep k from sweep k-1 only, Sec. 3.5
+// eq. (MCF)), so the result is bitwise that of T single-step launches.
+#include <hip/hip_runtime.h>
+
+#include "wmc_device.hpp"
+#include "wmc_internal.h"
+
+namespace wmc {
+
+constexpr int kBlock = 256;                 // 4 independent waves per workgroup
+constexpr int kWavesPerBlock = kBlock / 64;
+
+// Maps blockIdx.x so that the blocks the hardware places on one XCD (it deals
+// blocks round-robin over the 8 XCDs) process one contiguous range of work
+// items: neighbouring strips then share halo rows in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
+    const int64_t q = G / 8, r = G % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
+template <int C>
+struct Pref {
+    float u[C];
+    float f[C];
+};
+
+template <int C, bool DATA>
+__device__ __forceinline__ void load_row(Pref<C>& p, const float* __restrict__ src,
+                                         const float* __restrict__ fsrc, int64_t off, int xb,
+                                         int W, bool vec) {
+    const float* up = src + off;
+    const float* fp = DATA ? fsrc + off : nullptr;
+    if (vec && xb + C <= W) {
+        if constexpr (C == 4) {
+            const float4 v = *reinterpret_cast<const float4*>(up + xb);
+            p.u[0] = v.x; p.u[1] = v.y; p.u[2] = v.z; p.u[3] = v.w;
+            if constexpr (DATA) {
+                const float4 g = *reinterpret_cast<const float4*>(fp + xb);
+                p.f[0] = g.x; p.f[1] = g.y; p.f[2] = g.z; p.f[3] = g.w;
+            }
+        } else if constexpr (C == 2) {
+            const float2 v = *reinterpret_cast<const float2*>(up + xb);
+            p.u[0] = v.x; p.u[1] = v.y;
+            if constexpr (DATA) {
+                const float2 g = *reinterpret_cast<const float2*>(fp + xb);
+                p.f[0] = g.x; p.f[1] = g.y;
+            }
+        } else {
+            p.u[0] = up[xb];
+            if constexpr (DATA) p.f[0] = fp[xb];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < C; ++e) {
+            const int x = (xb + e < W) ? xb + e : W - 1;
+            p.u[e] = up[x];
+            if constexpr (DATA) p.f[e] = fp[x];
+        }
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void store_row(float* __restrict__ dst, int64_t off, int xb,
+                                          const float (&v)[C], const bool (&ok)[C], bool all_ok,
+                                          bool vec) {
+    float* p = dst + off + xb;
+    if (vec && all_ok) {
+        if constexpr (C == 4) {
+            *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+        } else if constexpr (C == 2) {
+            *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+        } else {
+            p[0] = v[0];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < C; ++e)
+            if (ok[e]) p[e] = v[e];
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void copy_row(RowQ<C>& d, const RowQ<C>& s) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        d.a[e] = s.a[e];
+        d.s[e] = s.s[e];
+        d.q[e] = s.q[e];
+        d.c[e] = s.c[e];
+    }
+}
+
+template <int P>
+struct Phase {
+    static constexpr int value = P;
+};
+
+// Everything a work item needs besides the register state.
+struct Item {
+    const float* src;
+    const float* f;
+    float* dst;
+    uint8_t* amap;
+    int64_t ld;
+    int H, W;
+    int x0, ox0, ox1;
+    int y0, y1;
+    bool vec;
+    Coef k;
+};
+
+template <int C, int T, int MODE, bool AM, bool RCL>
+__device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring) {
+    constexpr bool DATA = (MODE == kData);
+    constexpr int NS = T + 1;  // ring slots
+    const int lane = threadIdx.x & 63;
+    const int xb = it.x0 + C * lane;
+    const int H = it.H, W = it.W;
+
+    bool last[C], ok[C];
+    bool all_ok = true;
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        last[e] = (xb + e == W - 1);
+        ok[e] = (xb + e >= it.ox0) && (xb + e < it.ox1);
+        all_ok = all_ok && ok[e];
+    }
+
+    // rows of sweep k live in [lo_k, hi_k); sweep k computes row rho at step rho + k
+    const int lo0 = it.y0 - T > 0 ? it.y0 - T : 0;
+    const int hi0 = it.y1 + T < H ? it.y1 + T : H;
+    const int n_last = it.y1 - 1 + T;
+
+    RowQ<C> win[T][3];
+    Pref<C> pf[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        if (lo0 + j < hi0) load_row<C, DATA>(pf[j], it.src, it.f, (int64_t)(lo0 + j) * it.ld, xb, W, it.vec);
+
+    float* myring = ring + lane * C;
+
+    int n = lo0;
+    auto step = [&](auto phase_tag) {
+        constexpr int P = decltype(phase_tag)::value;
+        constexpr int PM = (P + 2) % 3;  // slot pushed one step ago
+        constexpr int PT = (P + 1) % 3;  // slot pushed two steps ago
+        // ---- sweep 0: the input row ------------------------------------------
+        if (n < hi0) {
+            float m[C];
+#pragma unroll
+            for (int e = 0; e < C; ++e) m[e] = pf[P].u[e];
+            if constexpr (DATA) {
+                float* slot = myring + (n % NS) * (64 * C);
+#pragma unroll
+                for (int e = 0; e < C; ++e) slot[e] = pf[P].f[e];
+            }
+            if (n + 3 < hi0)
+                load_row<C, DATA>(pf[P], it.src, it.f, (int64_t)(n + 3) * it.ld, xb, W, it.vec);
+            make_row<C, RCL>(m, last, win[0][P]);
+            if (n == 0) copy_row(win[0][PM], win[0][P]);  // row -1 := row 0 (top border)
+        }
+        // ---- sweeps 1..T --------------------------------------------------------
+#pragma unroll
+        for (int k = 1; k <= T; ++k) {
+            const int rho = n - k;
+            const int lo = it.y0 - (T - k) > 0 ? it.y0 - (T - k) : 0;
+            const int hi = it.y1 + (T - k) < H ? it.y1 + (T - k) : H;
+            if (rho >= lo && rho < hi) {
+                // bottom border: row H := row H-1.  Sweep k-1 did not produce a
+                // row this step, so its newest slot is free to hold the copy.
+                if (rho == H - 1) copy_row(win[k - 1][P], win[k - 1][PM]);
+                const RowQ<C>& t = win[k - 1][PT];
+                const RowQ<C>& mm = win[k - 1][PM];
+                const RowQ<C>& b = win[k - 1][P];
+                float fv[C];
+                if constexpr (DATA) {
+                    const float* slot = myring + (rho % NS) * (64 * C);
+#pragma unroll
+                    for (int e = 0; e < C; ++e) fv[e] = slot[e];
+                }
+                float v[C];
+                int idx[C];
+#pragma unroll
+                for (int e = 0; e < C; ++e) {
+                    const Odd o = parts(t.a[e], t.s[e], t.q[e], mm.s[e], mm.q[e], mm.c[e], b.a[e],
+                                        b.s[e], b.q[e]);
+                    float S;
+                    if constexpr (AM) S = select_x12_idx(o, idx[e]);
+                    else S = select_x12(o);
+                    if constexpr (MODE == kData) v[e] = update_data(mm.c[e], fv[e], S, it.k);
+                    else if constexpr (MODE == kFlow) v[e] = update_flow(mm.c[e], S, it.k);
+                    else v[e] = to_hd(S);
+                }
+                if (k < T) {
+                    // row rho of sweep k feeds sweep k+1 (index clamped only to keep
+                    // the never-taken k == T instance in bounds)
+                    RowQ<C>(&lv)[3] = win[k < T ? k : 0];
+                    make_row<C, RCL>(v, last, lv[P]);
+                    if (rho == 0) copy_row(lv[PM], lv[P]);  // row -1 := row 0
+                } else {
+                    const int64_t off = (int64_t)rho * it.ld;
+                    store_row<C>(it.dst, off, xb, v, ok, all_ok, it.vec);
+                    if constexpr (AM) {
+#pragma unroll
+                        for (int e = 0; e < C; ++e)
+                            if (ok[e]) it.amap[off + xb + e] = (uint8_t)idx[e];
+                    }
+                }
+            }
+        }
+    };
+
+    while (true) {
+        step(Phase<0>{});
+        if (++n > n_last) break;
+        step(Phase<1>{});
+        if (++n > n_last) break;
+        step(Phase<2>{});
+        if (++n > n_last) break;
+    }
+}
+
+// Resolves work item `item` of image d into an Item and runs it.
+template <int C, int T, int MODE, bool AM>
+__device__ __forceinline__ void process(const ImageDesc& d, int64_t local, const LaunchArgs& a,
+                                        float* ring) {
+    const int64_t per_plane = (int64_t)d.nseg * d.nstrip;
+    const int ch = (int)(local / per_plane);
+    const int rem = (int)(local - (int64_t)ch * per_plane);
+    const int seg = rem / d.nstrip;
+    const int strip = rem - seg * d.nstrip;
+
+    Item it;
+    const int64_t poff = (int64_t)ch * d.ps;
+    const float* srcb = a.src_sel == 0 ? d.src0 : (a.src_sel == 1 ? d.bufA : d.bufB);
+    float* dstb = a.dst_sel == 1 ? d.bufA : d.bufB;
+    it.src = srcb + poff;
+    it.f = d.f ? d.f + poff : nullptr;
+    it.dst = dstb + poff;
+    it.amap = d.amap ? d.amap + poff : nullptr;
+    it.ld = d.ld;
+    it.H = d.H;
+    it.W = d.W;
+    const int width = 64 * C, halo = halo_cols(C, T);
+    it.x0 = strip * (width - 2 * halo);
+    it.ox0 = strip == 0 ? 0 : it.x0 + halo;
+    it.ox1 = strip == d.nstrip - 1 ? d.W : it.x0 + width - halo;
+    it.y0 = seg * a.R;
+    it.y1 = it.y0 + a.R < d.H ? it.y0 + a.R : d.H;
+    it.vec = d.vec != 0;
+    const float lam = a.lam ? a.lam[d.lam_index + ch * d.lam_stride] : 0.0f;
+    it.k = make_coef(lam, a.dt, MODE == kData);
+    if (strip == d.nstrip - 1) run_item<C, T, MODE, AM, true>(it, ring);
+    else run_item<C, T, MODE, AM, false>(it, ring);
+}
+
+template <int C, int T, int MODE>
+constexpr int ring_floats() {
+    return MODE == kData ? kWavesPerBlock * (T + 1) * 64 * C : 1;
+}
+
+template <int C, int T, int MODE, bool AM>
+__global__ __launch_bounds__(kBlock) void k_stream_single(ImageDesc d, LaunchArgs a) {
+    __shared__ float ring[ring_floats<C, T, MODE>()];
+    // wave index, made visibly wave-uniform so that all work-item bookkeeping
+    // lives in scalar registers
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t total = (int64_t)d.channels * d.nseg * d.nstrip;
+    const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
+    if (item >= total) return;
+    process<C, T, MODE, AM>(d, item, a, ring + (MODE == kData ? wv * (T + 1) * 64 * C : 0));
+}
+
+// Persistent variant: a fixed grid of waves pulls work items of all images
+// from a global counter (one counter per launch, zeroed by a fill kernel).
+template <int C, int T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stream_batched(const ImageDesc* __restrict__ tbl,
+                                                           int nimg, int64_t total,
+                                                           LaunchArgs a,
+                                                           uint32_t* __restrict__ counter) {
+    __shared__ float ring[ring_floats<C, T, MODE>()];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    float* myring = ring + (MODE == kData ? wv * (T + 1) * 64 * C : 0);
+    while (true) {
+        uint32_t got = 0;
+        if (lane == 0) got = atomicAdd(counter, 1u);
+        const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane((int)got);
+        if (item >= total) break;
+        // binary search: last image whose item_base <= item
+        int lo = 0, hi = nimg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tbl[mid].item_base <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const ImageDesc d = tbl[lo];
+        process<C, T, MODE, false>(d, item - d.item_base, a, myring);
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_add_planes(const float* __restrict__ src, float* __restrict__ dst, int64_t h,
+                             int64_t w, int64_t ld, int64_t ps) {
+    const int64_t p = blockIdx.z;
+    const int64_t y = blockIdx.y;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < w;
+         x += (int64_t)gridDim.x * blockDim.x)
+        dst[p * ps + y * ld + x] += src[p * ps + y * ld + x];
+}
+
+__global__ void k_copy_planes(const float* __restrict__ src, float* __restrict__ dst, int64_t h,
+                              int64_t w, int64_t ld, int64_t ps) {
+    const int64_t p = blockIdx.z;
+    const int64_t y = blockIdx.y;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < w;
+         x += (int64_t)gridDim.x * blockDim.x)
+        dst[p * ps + y * ld + x] = src[p * ps + y * ld + x];
+}
+
+// Lane-shift self test: flags[0] = 1 iff from_lower_lane / from_upper_lane
+// move data as the kernels assume, for every lane of a wave.
+__global__ void k_selftest(int* flags) {
+    const int lane = threadIdx.x & 63;
+    const float me = (float)(lane + 1);
+    const float lo = from_lower_lane(-me, me);
+    const float up = from_upper_lane(-me, me);
+    const float want_lo = lane == 0 ? -me : (float)lane;
+    const float want_up = lane == 63 ? -me : (float)(lane + 2);
+    const bool good = (lo == want_lo) && (up == want_up);
+    const unsigned long long ballot = __ballot(good);
+    if (lane == 0) flags[threadIdx.x >> 6] = (ballot == ~0ull) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+using SingleFn = void (*)(ImageDesc, LaunchArgs);
+using BatchedFn = void (*)(const ImageDesc*, int, int64_t, LaunchArgs, uint32_t*);
+
+template <int C, int T, int MODE, bool AM>
+static SingleFn single_ptr() { return k_stream_single<C, T, MODE, AM>; }
+
+static int tindex(int T) {
+    switch (T) {
+        case 1: return 0;
+        case 2: return 1;
+        case 3: return 2;
+        case 4: return 3;
+        case 6: return 4;
+        case 8: return 5;
+        default: return -1;
+    }
+}
+static int cindex(int C) { return C == 1 ? 0 : (C == 2 ? 1 : (C == 4 ? 2 : -1)); }
+
+#define WMC_T_LIST(X, C, M) X(C, 1, M) X(C, 2, M) X(C, 3, M) X(C, 4, M) X(C, 6, M) X(C, 8, M)
+
+static SingleFn single_table(int C, int T, int mode, bool am) {
+    const int ci = cindex(C), ti = tindex(T);
+    if (ci < 0 || ti < 0) return nullptr;
+    if (mode == kModeCompute) {
+        if (T != 1) return nullptr;
+        static const SingleFn tab[3][2] = {
+            {k_stream_single<1, 1, kCompute, false>, k_stream_single<1, 1, kCompute, true>},
+            {k_stream_single<2, 1, kCompute, false>, k_stream_single<2, 1, kCompute, true>},
+            {k_stream_single<4, 1, kCompute, false>, k_stream_single<4, 1, kCompute, true>}};
+        return tab[ci][am ? 1 : 0];
+    }
+    if (am) {
+        if (T != 1) return nullptr;
+        static const SingleFn tab[3][2] = {
+            {k_stream_single<1, 1, kData, true>, k_stream_single<1, 1, kFlow, true>},
+            {k_stream_single<2, 1, kData, true>, k_stream_single<2, 1, kFlow, true>},
+            {k_stream_single<4, 1, kData, true>, k_stream_single<4, 1, kFlow, true>}};
+        return tab[ci][mode == kModeData ? 0 : 1];
+    }
+#define WMC_S(C, T, M) k_stream_single<C, T, M, false>,
+    static const SingleFn data_tab[3][6] = {{WMC_T_LIST(WMC_S, 1, kData)},
+                                            {WMC_T_LIST(WMC_S, 2, kData)},
+                                            {WMC_T_LIST(WMC_S, 4, kData)}};
+    static const SingleFn flow_tab[3][6] = {{WMC_T_LIST(WMC_S, 1, kFlow)},
+                                            {WMC_T_LIST(WMC_S, 2, kFlow)},
+                                            {WMC_T_LIST(WMC_S, 4, kFlow)}};
+#undef WMC_S
+    return mode == kModeData ? data_tab[ci][ti] : flow_tab[ci][ti];
+}
+
+static BatchedFn batched_table(int C, int T, int mode) {
+    const int ci = cindex(C), ti = tindex(T);
+    if (ci < 0 || ti < 0 || mode == kModeCompute) return nullptr;
+#define WMC_B(C, T, M) k_stream_batched<C, T, M>,
+    static const BatchedFn data_tab[3][6] = {{WMC_T_LIST(WMC_B, 1, kData)},
+                                             {WMC_T_LIST(WMC_B, 2, kData)},
+                                             {WMC_T_LIST(WMC_B, 4, kData)}};
+    static const BatchedFn flow_tab[3][6] = {{WMC_T_LIST(WMC_B, 1, kFlow)},
+                                             {WMC_T_LIST(WMC_B, 2, kFlow)},
+                                             {WMC_T_LIST(WMC_B, 4, kFlow)}};
+#undef WMC_B
+    return mode == kModeData ? data_tab[ci][ti] : flow_tab[ci][ti];
+}
+
+bool stream_variant_exists(int C, int T, int mode, bool argmin) {
+    return single_table(C, T, mode, argmin) != nullptr;
+}
+
+hipError_t launch_stream_single(int C, int T, int mode, bool argmin, const ImageDesc& d,
+                                const LaunchArgs& a, hipStream_t st) {
+    SingleFn fn = single_table(C, T, mode, argmin);
+    if (!fn) return hipErrorInvalidValue;
+    const int64_t total = (int64_t)d.channels * d.nseg * d.nstrip;
+    const int64_t blocks = (total + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, st, d, a);
+    return hipGetLastError();
+}
+
+int stream_blocks_per_cu(int C, int T, int mode) {
+    BatchedFn fn = batched_table(C, T, mode);
+    if (!fn) return 0;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn), kBlock,
+                                                     0) != hipSuccess)
+        return 0;
+    return nb;
+}
+
+hipError_t launch_stream_batched(int C, int T, int mode, const ImageDesc* dtable, int nimg,
+                                 int64_t total_items, const LaunchArgs& a, uint32_t* counter,
+                                 int grid_blocks, hipStream_t st) {
+    BatchedFn fn = batched_table(C, T, mode);
+    if (!fn || grid_blocks <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid_blocks), dim3(kBlock), 0, st, dtable, nimg,
+                       total_items, a, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_planes(const float* src, float* dst, int64_t n, int64_t h, int64_t w,
+                              int64_t ld, int64_t ps, hipStream_t st) {
+    if (n <= 0 || h <= 0 || w <= 0) return hipSuccess;
+    const int64_t gx = (w + 255) / 256 < 64 ? (w + 255) / 256 : 64;
+    if (h > 65535 || n > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy_planes, dim3((unsigned)gx, (unsigned)h, (unsigned)n), dim3(256), 0,
+                       st, src, dst, h, w, ld, ps);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_planes(const float* src, float* dst, int64_t n, int64_t h, int64_t w,
+                             int64_t ld, int64_t ps, hipStream_t st) {
+    if (n <= 0 || h <= 0 || w <= 0) return hipSuccess;
+    const int64_t gx = (w + 255) / 256 < 64 ? (w + 255) / 256 : 64;
+    if (h > 65535 || n > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_add_planes, dim3((unsigned)gx, (unsigned)h, (unsigned)n), dim3(256), 0,
+                       st, src, dst, h, w, ld, ps);
+    return hipGetLastError();
+}
+
+hipError_t launch_selftest(int* flags, hipStream_t st) {
+    hipLaunchKernelGGL(k_selftest, dim3(1), dim3(256), 0, st, flags);
+    return hipGetLastError();
+}
+
+}  // namespace wmc

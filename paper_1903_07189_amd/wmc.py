@@ -1,0 +1,343 @@
+"""ctypes binding of libwmc (include/wmc.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of libwmc.so; this module converts
+torch tensors (device memory owned by PyTorch) into the plain pointers, sizes
+and stream handle of the C ABI and raises on a non-zero status.  There is no
+fallback: if the library is missing or the device is not gfx950 the calls
+raise.
+
+Tensors are float32 CUDA tensors shaped (H, W) or (N, H, W) with unit stride
+along W; N planes are independent (colour channels or batch items).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwmc.so")
+
+WMC_OK, WMC_EINVAL, WMC_EHIP, WMC_ENOMEM, WMC_EUNSUPPORTED = 0, -1, -2, -3, -4
+
+
+class WMCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libwmc status {code}: {msg}")
+        self.code = code
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("h", ctypes.c_int64), ("w", ctypes.c_int64),
+                ("ld", ctypes.c_int64), ("ps", ctypes.c_int64)]
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("u0", ctypes.c_void_p), ("f", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("h", ctypes.c_int64), ("w", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("ps", ctypes.c_int64), ("channels", ctypes.c_int32), ("lam_index", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("cols", ctypes.c_int32), ("tsteps", ctypes.c_int32),
+                ("seg_rows", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+_lib = None
+EXPORTS = ["wmc_compute", "wmc_step", "wmc_solve_workspace", "wmc_set_stride",
+           "wmc_num_checkpoints", "wmc_solve",
+           "wmc_batched_workspace", "wmc_solve_batched", "wmc_autotune", "wmc_backward_workspace",
+           "wmc_backward", "wmc_selftest", "wmc_last_error", "wmc_release"]
+
+
+def lib():
+    """Loads libwmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                           "(or python paper_1903_07189_amd/_build.py) first")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, I64, F, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
+    L.wmc_compute.argtypes = [P, P, Shape, P]
+    L.wmc_step.argtypes = [P, P, P, P, F, P, Shape, P]
+    L.wmc_solve_workspace.argtypes = [Shape]
+    L.wmc_solve_workspace.restype = SZ
+    L.wmc_set_stride.argtypes = [Shape]
+    L.wmc_set_stride.restype = I64
+    L.wmc_num_checkpoints.argtypes = [I, I]
+    L.wmc_num_checkpoints.restype = I64
+    L.wmc_solve.argtypes = [P, P, P, P, I, F, P, I, ctypes.POINTER(Tuning), P, SZ, Shape, P]
+    L.wmc_batched_workspace.argtypes = [ctypes.POINTER(Image), I]
+    L.wmc_batched_workspace.restype = SZ
+    L.wmc_solve_batched.argtypes = [ctypes.POINTER(Image), I, P, I, F, ctypes.POINTER(Tuning), P,
+                                    SZ, P]
+    L.wmc_autotune.argtypes = [ctypes.POINTER(Image), I, I, ctypes.POINTER(Tuning), P, SZ, P]
+    L.wmc_backward_workspace.argtypes = [Shape, I, I]
+    L.wmc_backward_workspace.restype = SZ
+    L.wmc_backward.argtypes = [P, P, P, I, F, P, I, P, P, P, P, P, SZ, Shape, P]
+    L.wmc_selftest.argtypes = []
+    L.wmc_last_error.argtypes = []
+    L.wmc_last_error.restype = ctypes.c_char_p
+    L.wmc_release.argtypes = []
+    L.wmc_release.restype = None
+    for name in ("wmc_compute", "wmc_step", "wmc_solve", "wmc_solve_batched", "wmc_autotune",
+                 "wmc_backward", "wmc_selftest"):
+        getattr(L, name).restype = I
+    _lib = L
+    return L
+
+
+def check(code: int):
+    if code != WMC_OK:
+        raise WMCError(code, lib().wmc_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _planes(t: torch.Tensor) -> torch.Tensor:
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3:
+        raise ValueError("expected an (H, W) or (N, H, W) tensor")
+    if t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError("expected a float32 CUDA tensor")
+    if t.stride(2) != 1:
+        t = t.contiguous()
+    return t
+
+
+def shape_of(t: torch.Tensor) -> Shape:
+    t = _planes(t)
+    n, h, w = t.shape
+    return Shape(n, h, w, t.stride(1), t.stride(0) if n > 1 else h * t.stride(1))
+
+
+def _like(t: torch.Tensor) -> torch.Tensor:
+    """Uninitialised tensor with exactly t's strides (the ABI shares one layout)."""
+    return torch.empty_strided(t.shape, t.stride(), dtype=t.dtype, device=t.device)
+
+
+def _lam_tensor(lam, n: int, device) -> torch.Tensor:
+    if isinstance(lam, torch.Tensor):
+        lt = lam.detach().to(device=device, dtype=torch.float32).reshape(-1)
+        if lt.numel() == 1 and n > 1:
+            lt = lt.expand(n)
+        if lt.numel() != n:
+            raise ValueError(f"lam must hold 1 or {n} values")
+        return lt.contiguous()
+    return torch.full((n,), float(lam), dtype=torch.float32, device=device)
+
+
+def _tuning(tuning) -> Tuning | None:
+    if tuning is None:
+        return None
+    if isinstance(tuning, Tuning):
+        return tuning
+    d = dict(tuning)
+    return Tuning(int(d.get("cols", 0)), int(d.get("tsteps", 0)), int(d.get("seg_rows", 0)),
+                  int(d.get("use_graph", 1)))
+
+
+def compute(u: torch.Tensor) -> torch.Tensor:
+    """H_d(u): the Half Laplace Operator (Sec. 4.2)."""
+    squeeze = u.dim() == 2
+    u = _planes(u)
+    out = _like(u)
+    check(lib().wmc_compute(_ptr(u), _ptr(out), shape_of(u), _stream()))
+    return out[0] if squeeze else out
+
+
+def step(u: torch.Tensor, f: torch.Tensor | None = None, lam=1.0, dt: float = 0.0,
+         return_argmin: bool = False):
+    """One Jacobi update (data term if f is given, curvature flow otherwise)."""
+    squeeze = u.dim() == 2
+    u = _planes(u)
+    if f is not None:
+        f = _planes(f)
+        if f.shape != u.shape or f.stride() != u.stride():
+            f = f.contiguous() if u.is_contiguous() else f
+            if f.stride() != u.stride():
+                raise ValueError("u and f must share shape and layout")
+    out = _like(u)
+    lt = _lam_tensor(lam, u.shape[0], u.device) if f is not None else None
+    amap = torch.empty(u.shape, dtype=torch.uint8, device=u.device) if return_argmin else None
+    if amap is not None and (u.stride() != amap.stride()):
+        raise ValueError("argmin output needs a contiguous input")
+    check(lib().wmc_step(_ptr(u), _ptr(f), _ptr(out), _ptr(lt), float(dt), _ptr(amap),
+                         shape_of(u), _stream()))
+    if squeeze:
+        out = out[0]
+        amap = amap[0] if amap is not None else None
+    return (out, amap) if return_argmin else out
+
+
+def solve(f: torch.Tensor | None, lam=1.0, iters: int = 1, dt: float = 0.0,
+          u0: torch.Tensor | None = None, ckpt_every: int | None = None, tuning=None):
+    """iters Jacobi updates from u0 (default f).  With ckpt_every also returns
+    the checkpoint tensor (num_ckpt, N, H, W) that backward() restarts from."""
+    ref = f if f is not None else u0
+    if ref is None:
+        raise ValueError("need f or u0")
+    squeeze = ref.dim() == 2
+    ref = _planes(ref).contiguous()
+    f = None if f is None else _planes(f).contiguous()
+    u0 = None if u0 is None else _planes(u0).contiguous()
+    s = shape_of(ref)
+    L = lib()
+    out = torch.empty_like(ref)
+    ws = torch.empty(max(1, L.wmc_solve_workspace(s) // 4), dtype=torch.float32, device=ref.device)
+    lt = _lam_tensor(lam, ref.shape[0], ref.device) if f is not None else None
+    ck = None
+    if ckpt_every:
+        nck = L.wmc_num_checkpoints(int(iters), int(ckpt_every))
+        if L.wmc_set_stride(s) != ref.numel():
+            raise ValueError("checkpointing needs a contiguous plane set")
+        ck = torch.empty((max(nck, 1),) + tuple(ref.shape), dtype=torch.float32, device=ref.device)
+    tn = _tuning(tuning)
+    check(L.wmc_solve(_ptr(f), _ptr(u0), _ptr(out), _ptr(lt), int(iters), float(dt), _ptr(ck),
+                      int(ckpt_every or 0), ctypes.byref(tn) if tn else None, _ptr(ws),
+                      ws.numel() * 4, s, _stream()))
+    if squeeze:
+        out = out[0]
+    return (out, ck) if ckpt_every else out
+
+
+def backward(g_out: torch.Tensor, f: torch.Tensor | None, lam, iters: int, ckpt: torch.Tensor,
+             ckpt_every: int, dt: float = 0.0, u0: torch.Tensor | None = None):
+    """Reverse-mode derivative of L(U^iters) through solve(); returns
+    (g_f, g_u0, g_lam).  g_f includes the path through U^0 = f when u0 is None."""
+    ref = f if f is not None else u0
+    ref = _planes(ref).contiguous()
+    f = None if f is None else _planes(f).contiguous()
+    u0 = None if u0 is None else _planes(u0).contiguous()
+    g_out = _planes(g_out).contiguous()
+    s = shape_of(ref)
+    L = lib()
+    n = ref.shape[0]
+    lt = _lam_tensor(lam, n, ref.device) if f is not None else None
+    ws = torch.empty(max(1, L.wmc_backward_workspace(s, int(iters), int(ckpt_every)) // 4 + 64),
+                     dtype=torch.float32, device=ref.device)
+    g_f = torch.empty_like(ref) if f is not None else None
+    g_u0 = torch.empty_like(ref)
+    g_lam = torch.empty(n, dtype=torch.float32, device=ref.device) if f is not None else None
+    check(L.wmc_backward(_ptr(f), _ptr(u0), _ptr(lt), int(iters), float(dt), _ptr(ckpt),
+                         int(ckpt_every), _ptr(g_out), _ptr(g_f), _ptr(g_u0), _ptr(g_lam),
+                         _ptr(ws), ws.numel() * 4, s, _stream()))
+    return g_f, g_u0, g_lam
+
+
+def _images(fs, u0s, outs, lam_index):
+    arr = (Image * len(fs))()
+    for i, (f, u0, o) in enumerate(zip(fs, u0s, outs)):
+        ref = f if f is not None else u0
+        c, h, w = ref.shape
+        arr[i] = Image(_ptr(u0), _ptr(f), _ptr(o), h, w, ref.stride(1),
+                       ref.stride(0) if c > 1 else h * ref.stride(1), c, lam_index[i])
+    return arr
+
+
+def solve_batched(fs, lam, iters: int, dt: float = 0.0, u0s=None, tuning=None):
+    """Solves many (C, H, W) images of different sizes in one persistent,
+    graph-replayed launch sequence.  lam: one value per image (tensor or list)."""
+    fs = [None if f is None else _planes(f).contiguous() for f in fs]
+    u0s = [None] * len(fs) if u0s is None else [None if u is None else _planes(u).contiguous()
+                                                 for u in u0s]
+    refs = [f if f is not None else u for f, u in zip(fs, u0s)]
+    dev = refs[0].device
+    outs = [torch.empty_like(r) for r in refs]
+    lt = _lam_tensor(lam, len(fs), dev) if fs[0] is not None else None
+    arr = _images(fs, u0s, outs, list(range(len(fs))))
+    L = lib()
+    wsb = L.wmc_batched_workspace(arr, len(fs))
+    ws = torch.empty(max(1, wsb // 4), dtype=torch.float32, device=dev)
+    tn = _tuning(tuning)
+    check(L.wmc_solve_batched(arr, len(fs), _ptr(lt), int(iters), float(dt),
+                              ctypes.byref(tn) if tn else None, _ptr(ws), ws.numel() * 4,
+                              _stream()))
+    return outs
+
+
+class SolveBatchedPlan:
+    """Pre-marshalled batched solve for repeated calls on the same buffers
+    (keeps the descriptor array and workspace alive; the library replays its
+    cached graph)."""
+
+    def __init__(self, fs, lam, iters: int, dt: float = 0.0, outs=None, tuning=None):
+        self.fs = [_planes(f).contiguous() for f in fs]
+        dev = self.fs[0].device
+        self.outs = outs if outs is not None else [torch.empty_like(f) for f in self.fs]
+        self.lam = _lam_tensor(lam, len(self.fs), dev)
+        self.arr = _images(self.fs, [None] * len(self.fs), self.outs, list(range(len(self.fs))))
+        L = lib()
+        self.ws = torch.empty(max(1, L.wmc_batched_workspace(self.arr, len(self.fs)) // 4),
+                              dtype=torch.float32, device=dev)
+        self.iters, self.dt = int(iters), float(dt)
+        self.tuning = _tuning(tuning)
+
+    def __call__(self):
+        check(lib().wmc_solve_batched(self.arr, len(self.fs), _ptr(self.lam), self.iters, self.dt,
+                                      ctypes.byref(self.tuning) if self.tuning else None,
+                                      _ptr(self.ws), self.ws.numel() * 4, _stream()))
+        return self.outs
+
+
+def autotune(fs, iters: int = 100):
+    """Runs the library's autotuner on a batch; returns the chosen tuning dict."""
+    fs = [_planes(f).contiguous() for f in fs]
+    outs = [torch.empty_like(f) for f in fs]
+    arr = _images(fs, [None] * len(fs), outs, [0] * len(fs))
+    L = lib()
+    ws = torch.empty(max(1, L.wmc_batched_workspace(arr, len(fs)) // 4), dtype=torch.float32,
+                     device=fs[0].device)
+    t = Tuning()
+    check(L.wmc_autotune(arr, len(fs), int(iters), ctypes.byref(t), _ptr(ws), ws.numel() * 4,
+                         _stream()))
+    return {"cols": t.cols, "tsteps": t.tsteps, "seg_rows": t.seg_rows, "use_graph": t.use_graph}
+
+
+def selftest():
+    check(lib().wmc_selftest())
+
+
+def release():
+    lib().wmc_release()
+
+
+class WMCSolve(torch.autograd.Function):
+    """U^K = solve(f, lam, K) as a differentiable layer: forward runs the fused
+    solver storing a checkpoint every ckpt_every steps (default ceil(sqrt(K))),
+    backward runs the hand-written adjoint, recomputing each segment from its
+    checkpoint.  Gradients flow to f (N, H, W) and to lam (N,)."""
+
+    @staticmethod
+    def forward(ctx, f, lam, K: int, dt: float = 0.0, ckpt_every: int | None = None, tuning=None):
+        K = int(K)
+        c = int(ckpt_every) if ckpt_every else max(1, int(-(-K ** 0.5 // 1)))
+        lam_t = _lam_tensor(lam, _planes(f).shape[0], f.device)
+        out, ck = solve(f.detach(), lam_t, K, dt=dt, ckpt_every=c, tuning=tuning)
+        ctx.save_for_backward(f.detach(), lam_t, ck)
+        ctx.K, ctx.c, ctx.dt = K, c, float(dt)
+        ctx.lam_is_tensor = isinstance(lam, torch.Tensor)
+        ctx.lam_shape = tuple(lam.shape) if ctx.lam_is_tensor else None
+        ctx.lam_numel = lam.numel() if ctx.lam_is_tensor else 0
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        f, lam_t, ck = ctx.saved_tensors
+        g_f, _, g_lam = backward(g.contiguous(), f, lam_t, ctx.K, ck, ctx.c, dt=ctx.dt)
+        g_f = g_f.reshape(f.shape)
+        gl = None
+        if ctx.lam_is_tensor:
+            gl = g_lam.reshape(ctx.lam_shape) if ctx.lam_numel == g_lam.numel() else \
+                g_lam.sum().reshape(ctx.lam_shape)
+        return g_f, gl, None, None, None, None

@@ -1,0 +1,157 @@
+"""Host-side tests of the C ABI: the library loads, exports every function the
+header declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wmc.h")
+
+
+def _declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(wmc_[a-z_]+)\s*\(", txt, re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def wmc():
+    from paper_1903_07189_amd import wmc as W
+    if not os.path.exists(W.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return W
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for want in ["wmc_compute", "wmc_step", "wmc_solve", "wmc_solve_batched", "wmc_backward",
+                 "wmc_autotune", "wmc_last_error", "wmc_release"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(wmc):
+    L = wmc.lib()
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+    assert set(_declared_functions()) == set(wmc.EXPORTS)
+
+
+def test_workspace_queries(wmc):
+    L = wmc.lib()
+    S = wmc.Shape
+    assert L.wmc_solve_workspace(S(1, 4096, 4096, 4096, 4096 * 4096)) == 4096 * 4096 * 4
+    assert L.wmc_solve_workspace(S(3, 10, 10, 12, 130)) == 3 * 130 * 4
+    assert L.wmc_solve_workspace(S(0, 10, 10, 10, 100)) == 0
+    assert L.wmc_set_stride(S(1, 5, 7, 8, 0)) == 4 * 8 + 7
+    assert L.wmc_num_checkpoints(20, 5) == 4
+    assert L.wmc_num_checkpoints(21, 5) == 5
+    assert L.wmc_num_checkpoints(0, 5) == 0
+    assert L.wmc_backward_workspace(S(1, 32, 32, 32, 1024), 20, 5) > 0
+    assert L.wmc_backward_workspace(S(1, 32, 32, 32, 1024), 20, 0) == 0
+
+
+P = ctypes.c_void_p
+
+
+@pytest.mark.parametrize("shape,msg", [
+    ((0, 4, 4, 4, 16), "n, h and w"),
+    ((1, 0, 4, 4, 16), "n, h and w"),
+    ((1, 4, 4, 3, 16), "ld must be"),
+    ((2, 4, 4, 4, 10), "ps must be"),
+    ((1, 1 << 30, 4, 4, 16), "2^30"),
+])
+def test_shape_validation(wmc, shape, msg):
+    L = wmc.lib()
+    rc = L.wmc_compute(P(4096), P(1 << 20), wmc.Shape(*shape), None)
+    assert rc == wmc.WMC_EINVAL
+    assert msg in L.wmc_last_error().decode()
+
+
+def test_step_validation(wmc):
+    L = wmc.lib()
+    S = wmc.Shape(1, 4, 4, 4, 16)
+    assert L.wmc_step(None, None, P(1 << 20), None, 0.0, None, S, None) == wmc.WMC_EINVAL
+    # data term without lambda
+    assert L.wmc_step(P(4096), P(8192), P(1 << 20), None, 0.0, None, S, None) == wmc.WMC_EINVAL
+    assert "lam" in L.wmc_last_error().decode()
+    # in-place update is rejected: Jacobi updates read every pixel of U^t
+    assert L.wmc_step(P(4096), None, P(4096 + 16), None, 0.0, None, S, None) == wmc.WMC_EINVAL
+    assert "overlap" in L.wmc_last_error().decode()
+    assert L.wmc_step(P(4096), None, P(1 << 20), None, float("nan"), None, S, None) == wmc.WMC_EINVAL
+
+
+def test_solve_validation(wmc):
+    L = wmc.lib()
+    S = wmc.Shape(1, 8, 8, 8, 64)
+    # flow mode needs u0
+    assert L.wmc_solve(None, None, P(1 << 20), None, 3, 0.0, None, 0, None, P(1 << 21), 1 << 12,
+                       S, None) == wmc.WMC_EINVAL
+    # negative iterations
+    assert L.wmc_solve(P(4096), None, P(1 << 20), P(64), -1, 0.0, None, 0, None, P(1 << 21),
+                       1 << 12, S, None) == wmc.WMC_EINVAL
+    # workspace too small
+    assert L.wmc_solve(P(4096), None, P(1 << 20), P(64), 5, 0.0, None, 0, None, P(1 << 21), 16, S,
+                       None) == wmc.WMC_ENOMEM
+    # checkpoints without a period
+    assert L.wmc_solve(P(4096), None, P(1 << 20), P(64), 5, 0.0, P(1 << 22), 0, None, P(1 << 21),
+                       1 << 12, S, None) == wmc.WMC_EINVAL
+    # output aliasing the workspace
+    assert L.wmc_solve(P(4096), None, P(1 << 20), P(64), 5, 0.0, None, 0, None, P(1 << 20),
+                       1 << 12, S, None) == wmc.WMC_EINVAL
+    # bad tuning
+    t = wmc.Tuning(3, 4, 16, 1)
+    assert L.wmc_solve(P(4096), None, P(1 << 20), P(64), 5, 0.0, None, 0, ctypes.byref(t),
+                       P(1 << 21), 1 << 12, S, None) in (wmc.WMC_EINVAL, wmc.WMC_EHIP)
+
+
+def test_batched_validation(wmc):
+    L = wmc.lib()
+    imgs = (wmc.Image * 2)()
+    imgs[0] = wmc.Image(None, P(4096), P(1 << 20), 8, 8, 8, 64, 1, 0)
+    imgs[1] = wmc.Image(P(8192), None, P(1 << 21), 8, 8, 8, 64, 1, 0)  # mixed modes
+    assert L.wmc_solve_batched(imgs, 2, P(64), 3, 0.0, None, P(1 << 22), 1 << 16, None) == wmc.WMC_EINVAL
+    imgs[1] = wmc.Image(None, P(8192), P(1 << 20), 8, 8, 8, 64, 1, 0)  # outputs overlap
+    assert L.wmc_solve_batched(imgs, 2, P(64), 3, 0.0, None, P(1 << 22), 1 << 16, None) == wmc.WMC_EINVAL
+    assert L.wmc_batched_workspace(imgs, 2) == 2 * 64 * 4
+
+
+def test_backward_validation(wmc):
+    L = wmc.lib()
+    S = wmc.Shape(1, 8, 8, 8, 64)
+    assert L.wmc_backward(P(4096), None, P(64), 5, 0.0, None, 2, P(1 << 20), P(1 << 21), None,
+                          None, P(1 << 22), 1 << 16, S, None) == wmc.WMC_EINVAL  # no ckpt
+    assert L.wmc_backward(P(4096), None, P(64), 5, 0.0, P(1 << 23), 2, P(1 << 20), P(1 << 21),
+                          None, None, P(1 << 22), 8, S, None) == wmc.WMC_ENOMEM
+
+
+def test_valid_call_without_device_reports_hip_error(wmc):
+    """A valid call on a machine without a gfx950 device fails cleanly (no
+    crash), with a HIP or unsupported-device status."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L = wmc.lib()
+    rc = L.wmc_compute(P(4096), P(1 << 20), wmc.Shape(1, 4, 4, 4, 16), None)
+    assert rc in (wmc.WMC_EHIP, wmc.WMC_EUNSUPPORTED)
+    assert L.wmc_last_error()
+
+
+def test_fault_injection_paths(wmc, monkeypatch):
+    """WMC_FAULT_INJECT makes the library report a HIP failure from host code."""
+    L = wmc.lib()
+    monkeypatch.setenv("WMC_FAULT_INJECT", "launch")
+    rc = L.wmc_compute(P(4096), P(1 << 20), wmc.Shape(1, 4, 4, 4, 16), None)
+    assert rc == wmc.WMC_EHIP
+    assert "injected" in L.wmc_last_error().decode()
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1903_07189_amd import wmc as W
+    monkeypatch.setattr(W, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(W, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        W.lib()
