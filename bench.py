@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Throughput of the WMC-regularised denoising solver on one MI355X.
+
+One "step" is one whole solve of the plain WMC denoising problem on the
+4096 x 4096 fp32 workload: 200 Jacobi updates
+U <- U + dt[(f - U) + lam H_d(U)] (lam = 1, default dt = 1/(1+lam)), every
+update evaluating the Half Laplace Operator at every pixel, from U^0 = f, with
+f and the state resident in HBM.  The library fuses several updates per pass
+over memory (temporal blocking) and replays the launch sequence as a hipGraph.
+
+Printed: one JSON line with the metric (Gpixel-iterations/s), the roofline
+of the dominant kernel measured with HIP events on the stream the graph runs
+on, the FP64 CPU oracle timed on a bounded sample, and extras: the plain
+single-update kernel's HBM bandwidth and the uneven-size batched solve against
+per-image plain launches.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpixel-iter/s of WMC step (fp32) and % HBM roofline; batched vs per-image"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz = 39.3
+# Arithmetic of one pixel update in the column-sum form:
+# row quantities 3 + odd/even parts 11 + candidates 8 + selection 14 + update 3.
+ALGO_OPS_PER_PX_ITER = 39
+BYTES_PER_PX_PASS = 12         # read U and f, write U' once per pass over memory
+
+
+def depths(iters: int, T: int):
+    """Launch depths the library uses for `iters` sweeps at maximum depth T."""
+    out = []
+    allowed = (8, 6, 4, 3, 2, 1)
+    while iters > 0:
+        t = min(iters, T)
+        t = next(d for d in allowed if d <= t)
+        out.append(t)
+        iters -= t
+    return out
+
+
+def kernel_sha():
+    h = hashlib.sha256()
+    for name in ("wmc_stream.hip", "wmc_device.hpp"):
+        with open(os.path.join(ROOT, "paper_1903_07189_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(tuning, side):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source and launch shape."""
+    path = os.path.join(ROOT, "profiles", f"stream_kernel_{side}_counters.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    try:
+        if kv.get("kernel_sha") != kernel_sha():
+            return None
+        if kv.get("tuning") != f"{tuning['cols']},{tuning['tsteps']},{tuning['seg_rows']}":
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(side: int, sample_iters: int):
+    """The FP64 oracle (single thread, pinned to one core) on the same input."""
+    import numpy as np
+    import oracle
+    import wmc_synth
+    try:
+        os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})
+    except (AttributeError, OSError):
+        pass
+    noisy, _ = wmc_synth.c2(side=side)
+    f = noisy[0].astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.solve(f, lam=1.0, iters=sample_iters)
+    dt = time.perf_counter() - t0
+    return {"value": round(side * side * sample_iters / dt / 1e9, 6), "unit": "Gpixel-iter/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{side}x{side} input, {sample_iters} of the 200 iterations "
+                      f"({dt:.1f} s, FP64, one thread)"}
+
+
+def timed(fn, reps, stream, torch):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--iters", type=int, default=200)
+    ap.add_argument("--side", type=int, default=4096)
+    ap.add_argument("--no-extras", action="store_true", help="skip the step/batched extras")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=5)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration for rocprofv3)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import wmc_synth
+    import paper_1903_07189_amd as wmc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calibration:
+        a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_dispatch": a.numel() * 4,
+                          "copy_bytes_written_per_dispatch": a.numel() * 4}))
+        return
+
+    wmc.selftest()
+    side, iters = args.side, args.iters
+    noisy, _ = wmc_synth.c2(side=side)
+    f = torch.from_numpy(noisy).to(dev)           # (1, side, side)
+    lam = torch.tensor([1.0], device=dev)
+
+    tuning = wmc.solve_tuning(f, lam)             # autotuned once (cached) before timing
+    plan = wmc.SolvePlan(f, lam, iters, tuning=tuning)
+    for _ in range(args.warmup):
+        plan()
+    torch.cuda.synchronize()
+
+    ms = timed(plan, args.steps, stream, torch)
+    ms_per_step = ms / args.steps
+    px_iter = side * side * iters
+    value = px_iter / (ms_per_step * 1e-3) / 1e9
+
+    launches = depths(iters, tuning["tsteps"])
+    avg_launch_ms = ms_per_step / len(launches)
+    mean_T = iters / len(launches)
+    # dominant kernel: the fused streaming kernel; both of its bounds
+    alu_achieved = ALGO_OPS_PER_PX_ITER * side * side * mean_T / (avg_launch_ms * 1e-3) / 1e12
+    hbm_achieved = BYTES_PER_PX_PASS * side * side / (avg_launch_ms * 1e-3) / 1e9
+    traffic = read_traffic(tuning, side)
+    roof_alu = {"bound": "alu", "achieved": round(alu_achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                "unit": "Tops/s", "frac": round(alu_achieved / ALU_PEAK_TOPS, 4), "traffic": traffic}
+    roof_hbm = {"bound": "hbm", "achieved": round(hbm_achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hbm_achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+    roofline = roof_alu if roof_alu["frac"] >= roof_hbm["frac"] else roof_hbm
+    other = roof_hbm if roofline is roof_alu else roof_alu
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Gpixel-iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"plain WMC denoising solve, {side}x{side} fp32 piecewise-smooth "
+                               f"synthetic + Gaussian noise sigma 0.1 (seed 1), {iters} iterations, "
+                               "lam 1, dt 1/(1+lam)",
+                   "side": side, "iters": iters, "lam": 1.0, "tuning": tuning,
+                   "launches_per_step": len(launches), "kernel": "k_stream_single (fused, "
+                   f"{tuning['tsteps']} sweeps/launch)"},
+        "roofline": roofline,
+        "roofline_other_bound": other,
+        "step_equivalent_hbm_frac": round(BYTES_PER_PX_PASS * value / HBM_PEAK_GBS, 4),
+        "paper_context": "33.2 Gpixel/s for the operator alone on an NVIDIA TITAN X (Pascal), "
+                         "workload unstated (context only)",
+    }
+
+    if not args.no_extras:
+        out["extras"] = extras(torch, wmc, wmc_synth, f, lam, stream, side)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(side, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+def extras(torch, wmc, wmc_synth, f, lam, stream, side):
+    ex = {}
+    # plain single-update kernel (one launch per iteration, graph-replayed)
+    t1 = {"cols": 4, "tsteps": 1, "seg_rows": 64, "use_graph": 1}
+    reps = 50
+    p1 = wmc.SolvePlan(f, lam, reps, tuning=t1)
+    p1()
+    ms = timed(p1, 3, stream, torch) / 3
+    per_launch = ms / reps
+    gbs = BYTES_PER_PX_PASS * side * side / (per_launch * 1e-3) / 1e9
+    ex["step_T1_4096"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                          "gpx_per_s": round(side * side / (per_launch * 1e-3) / 1e9, 2),
+                          "note": "warm: the 192 MiB working set fits the 256 MB Infinity Cache"}
+    # 8192^2 control, larger than the Infinity Cache
+    g = torch.rand((1, 8192, 8192), device=f.device)
+    p2 = wmc.SolvePlan(g, lam, 20, tuning=t1)
+    p2()
+    ms = timed(p2, 2, stream, torch) / 2
+    per_launch = ms / 20
+    gbs = BYTES_PER_PX_PASS * 8192 * 8192 / (per_launch * 1e-3) / 1e9
+    ex["step_T1_8192"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    del g, p2
+    # operator alone (read U, write H)
+    h = wmc.compute(f)
+    ms = timed(lambda: wmc.compute(f), 20, stream, torch) / 20
+    ex["compute_4096"] = {"gpx_per_s": round(side * side / (ms * 1e-3) / 1e9, 1),
+                          "gbs_incl_launch": round(8 * side * side / (ms * 1e-3) / 1e9, 1)}
+    del h
+    # uneven batch: 64 images x 3 channels, sides U{128..2048}, 100 iterations
+    sizes = wmc_synth.c3_sizes()
+    imgs = []
+    for b, (hh, ww, sig) in enumerate(sizes):
+        noisy, _ = wmc_synth.c3_image(b, hh, ww, sig)
+        imgs.append(torch.from_numpy(noisy).to(f.device))
+    lams = torch.ones(len(imgs), device=f.device)
+    px = sum(int(x.numel()) for x in imgs)
+    bp = wmc.SolveBatchedPlan(imgs, lams, 100)
+    bp()  # autotunes once
+    ms_b = timed(bp, 3, stream, torch) / 3
+    # per-image plain form: per image one single-update launch per iteration, no graph
+    plain = {"cols": 2, "tsteps": 1, "seg_rows": 32, "use_graph": 0}
+    plans = [wmc.SolvePlan(x, lams[i:i + 1].expand(x.shape[0]).contiguous(), 100, tuning=plain)
+             for i, x in enumerate(imgs)]
+
+    def run_plain():
+        for p in plans:
+            p()
+    run_plain()
+    ms_p = timed(run_plain, 2, stream, torch) / 2
+    ex["batched_c3"] = {"channel_px": px, "iters": 100,
+                        "batched_gpx_iter_s": round(px * 100 / (ms_b * 1e-3) / 1e9, 2),
+                        "per_image_plain_gpx_iter_s": round(px * 100 / (ms_p * 1e-3) / 1e9, 2),
+                        "speedup": round(ms_p / ms_b, 2), "ms_batched": round(ms_b, 3),
+                        "ms_per_image_plain": round(ms_p, 3),
+                        "per_image_plain_launches": 100 * len(imgs)}
+    return ex
+
+
+if __name__ == "__main__":
+    main()

@@ -130,6 +130,12 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
               float dt, float* ckpt, int ckpt_every, const wmc_tuning* tune, void* ws,
               size_t ws_bytes, wmc_shape s, void* stream);
 
+/* The launch shape wmc_solve(f, u0, ..., tune = NULL) uses for this shape:
+ * the cached autotuner result, or a fresh search timed on ws (which it may
+ * overwrite; nothing else is written).  Arguments as for wmc_solve. */
+int wmc_solve_tuning(const float* f, const float* u0, const float* lam, float dt, void* ws,
+                     size_t ws_bytes, wmc_shape s, wmc_tuning* out, void* stream);
+
 /* Bytes of workspace wmc_solve_batched needs for this batch. */
 size_t wmc_batched_workspace(const wmc_image* imgs, int n_imgs);
 

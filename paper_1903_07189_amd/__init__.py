@@ -5,8 +5,9 @@ Jacobi iterations (Sec. 3.5, Sec. 5.2) -- runs in hand-written HIP kernels for
 gfx950 behind the C ABI of include/wmc.h (libwmc.so).  This package is the
 thin Python binding of that ABI; see :mod:`paper_1903_07189_amd.wmc`.
 """
-from .wmc import (WMCError, WMCSolve, SolveBatchedPlan, autotune, backward, compute, lib,
-                  release, selftest, shape_of, solve, solve_batched, step)
+from .wmc import (WMCError, WMCSolve, SolveBatchedPlan, SolvePlan, autotune, backward, compute,
+                  lib, release, selftest, shape_of, solve, solve_batched, solve_tuning, step)
 
-__all__ = ["WMCError", "WMCSolve", "SolveBatchedPlan", "autotune", "backward", "compute", "lib",
-           "release", "selftest", "shape_of", "solve", "solve_batched", "step"]
+__all__ = ["WMCError", "WMCSolve", "SolveBatchedPlan", "SolvePlan", "autotune", "backward",
+           "compute", "lib", "release", "selftest", "shape_of", "solve", "solve_batched",
+           "solve_tuning", "step"]

@@ -160,10 +160,11 @@ void split_run(int len, int T, std::vector<int>& out) {
     }
 }
 
-// Output rows per work item: aim for >= ~8 waves per CU.
+// Output rows per work item: aim for ~16 waves per CU (memory latency hiding
+// for the single-sweep kernels).
 int default_rows(int64_t planes, int64_t h, int64_t w, int C, int T, int ncu) {
     const int64_t strips = strip_count((int)w, C, T);
-    const int64_t target = (int64_t)ncu * 8;
+    const int64_t target = (int64_t)ncu * 16;
     int64_t per_col = std::max<int64_t>(1, target / std::max<int64_t>(1, strips * planes));
     int64_t R = (h + per_col - 1) / per_col;
     R = std::max<int64_t>(R, 4 * (int64_t)T);
@@ -567,9 +568,9 @@ int tune_search(Run&& run, int64_t h_max, hipStream_t st, Tuned* best_out) {
     int rc = WMC_OK;
     for (int C : {1, 2, 4})
         for (int T : {1, 2, 3, 4, 6, 8})
-            for (int R : {16, 32, 64, 128}) {
+            for (int R : {8, 16, 32, 64, 128}) {
                 if (R < 2 * T && R < h_max) continue;
-                if (R > 2 * h_max && R != 16) continue;
+                if (R > 2 * h_max && R != 8) continue;
                 // warm up once, then take the best of three
                 rc = run(C, T, R, st);
                 if (rc) goto done;
@@ -792,7 +793,7 @@ int wmc_compute(const float* u, float* hw, wmc_shape s, void* stream) {
     int dev;
     rc = check_device(&dev);
     if (rc) return rc;
-    const int C = vec_cols({u, hw}, s.ld, s.n > 1 ? s.ps : 0);
+    const int C = std::min(2, vec_cols({u, hw}, s.ld, s.n > 1 ? s.ps : 0));
     const int R = default_rows(s.n, s.h, s.w, C, 1, num_cu(dev));
     ImageDesc d{};
     d.src0 = u;
@@ -833,7 +834,7 @@ int wmc_step(const float* u, const float* f, float* u_out, const float* lam, flo
     rc = check_device(&dev);
     if (rc) return rc;
     const int mode = f ? kModeData : kModeFlow;
-    const int C = vec_cols({u, f, u_out}, s.ld, s.n > 1 ? s.ps : 0);
+    const int C = std::min(2, vec_cols({u, f, u_out}, s.ld, s.n > 1 ? s.ps : 0));
     const int R = default_rows(s.n, s.h, s.w, C, 1, num_cu(dev));
     ImageDesc d{};
     d.src0 = u;
@@ -939,6 +940,33 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
     key_add(key, dev);
     auto prepare = [](PlanEntry&) { return WMC_OK; };
     return run_plan(key, dev, st, true, prepare, enqueue);
+}
+
+int wmc_solve_tuning(const float* f, const float* u0, const float* lam, float dt, void* ws,
+                     size_t ws_bytes, wmc_shape s, wmc_tuning* out, void* stream) {
+    g_err.clear();
+    int rc = check_shape(s);
+    if (rc) return rc;
+    if (!out) return fail(WMC_EINVAL, "wmc_solve_tuning: null out");
+    if (!f && !u0) return fail(WMC_EINVAL, "wmc_solve_tuning: the curvature flow needs u0");
+    if (f && !lam) return fail(WMC_EINVAL, "wmc_solve_tuning: lam is required with a data term");
+    if (!ws || ws_bytes < wmc_solve_workspace(s))
+        return fail(WMC_ENOMEM, "wmc_solve_tuning: workspace smaller than wmc_solve_workspace()");
+    const int64_t ext = extent_elems(s);
+    const Range rw = range_of(ws, ext, 4);
+    if (overlaps(rw, range_of(f, ext, 4)) || overlaps(rw, range_of(u0, ext, 4)))
+        return fail(WMC_EINVAL, "wmc_solve_tuning: ws overlaps an input");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    Tuned t{};
+    rc = tune_single(dev, s, u0 ? u0 : f, f, lam, dt, static_cast<float*>(ws), as_stream(stream), &t);
+    if (rc) return rc;
+    out->cols = t.C;
+    out->tsteps = t.T;
+    out->seg_rows = t.R;
+    out->use_graph = 1;
+    return WMC_OK;
 }
 
 size_t wmc_batched_workspace(const wmc_image* imgs, int n_imgs) {

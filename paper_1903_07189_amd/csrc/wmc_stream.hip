@@ -41,61 +41,6 @@ struct Pref {
     float f[C];
 };
 
-template <int C, bool DATA>
-__device__ __forceinline__ void load_row(Pref<C>& p, const float* __restrict__ src,
-                                         const float* __restrict__ fsrc, int64_t off, int xb,
-                                         int W, bool vec) {
-    const float* up = src + off;
-    const float* fp = DATA ? fsrc + off : nullptr;
-    if (vec && xb + C <= W) {
-        if constexpr (C == 4) {
-            const float4 v = *reinterpret_cast<const float4*>(up + xb);
-            p.u[0] = v.x; p.u[1] = v.y; p.u[2] = v.z; p.u[3] = v.w;
-            if constexpr (DATA) {
-                const float4 g = *reinterpret_cast<const float4*>(fp + xb);
-                p.f[0] = g.x; p.f[1] = g.y; p.f[2] = g.z; p.f[3] = g.w;
-            }
-        } else if constexpr (C == 2) {
-            const float2 v = *reinterpret_cast<const float2*>(up + xb);
-            p.u[0] = v.x; p.u[1] = v.y;
-            if constexpr (DATA) {
-                const float2 g = *reinterpret_cast<const float2*>(fp + xb);
-                p.f[0] = g.x; p.f[1] = g.y;
-            }
-        } else {
-            p.u[0] = up[xb];
-            if constexpr (DATA) p.f[0] = fp[xb];
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < C; ++e) {
-            const int x = (xb + e < W) ? xb + e : W - 1;
-            p.u[e] = up[x];
-            if constexpr (DATA) p.f[e] = fp[x];
-        }
-    }
-}
-
-template <int C>
-__device__ __forceinline__ void store_row(float* __restrict__ dst, int64_t off, int xb,
-                                          const float (&v)[C], const bool (&ok)[C], bool all_ok,
-                                          bool vec) {
-    float* p = dst + off + xb;
-    if (vec && all_ok) {
-        if constexpr (C == 4) {
-            *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-        } else if constexpr (C == 2) {
-            *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
-        } else {
-            p[0] = v[0];
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < C; ++e)
-            if (ok[e]) p[e] = v[e];
-    }
-}
-
 template <int C>
 __device__ __forceinline__ void copy_row(RowQ<C>& d, const RowQ<C>& s) {
 #pragma unroll
@@ -105,6 +50,15 @@ __device__ __forceinline__ void copy_row(RowQ<C>& d, const RowQ<C>& s) {
         d.q[e] = s.q[e];
         d.c[e] = s.c[e];
     }
+}
+
+// A copy that stays behind a real (uniform) branch: without the barrier the
+// compiler if-converts the rare border copies into selects executed at every
+// row step.
+template <int C>
+__device__ __forceinline__ void rare_copy(RowQ<C>& d, const RowQ<C>& s) {
+    __asm__ volatile("" ::: "memory");
+    copy_row(d, s);
 }
 
 template <int P>
@@ -126,21 +80,41 @@ struct Item {
     Coef k;
 };
 
-template <int C, int T, int MODE, bool AM, bool RCL>
+// Global memory access with a wave-uniform row pointer and a 32-bit per-lane
+// byte offset, so that the loads and stores use the scalar-base addressing
+// form (no 64-bit address arithmetic per lane).
+template <class V>
+__device__ __forceinline__ V ld_at(const float* row, uint32_t col) {
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(row) + col * 4u);
+}
+template <class V>
+__device__ __forceinline__ void st_at(float* row, uint32_t col, V v) {
+    *reinterpret_cast<V*>(reinterpret_cast<char*>(row) + col * 4u) = v;
+}
+
+// Runs one work item: rows of T sweeps pipelined in registers (see top of
+// file).  RCL: this strip holds the last image column (replicate clamp inside
+// the wave, scalar clamped loads).  VEC: rows are 4C-byte aligned and the
+// strip lies inside the image, so every lane moves its C columns with one
+// vector access.
+template <int C, int T, int MODE, bool AM, bool RCL, bool VEC>
 __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring) {
     constexpr bool DATA = (MODE == kData);
-    constexpr int NS = T + 1;  // ring slots
+    constexpr int NS = T + 1;  // f ring slots
     const int lane = threadIdx.x & 63;
     const int xb = it.x0 + C * lane;
     const int H = it.H, W = it.W;
+    static_assert(!(RCL && VEC), "the border strip uses clamped scalar loads");
 
     bool last[C], ok[C];
+    int xc[C];  // clamped columns for scalar loads
     bool all_ok = true;
 #pragma unroll
     for (int e = 0; e < C; ++e) {
         last[e] = (xb + e == W - 1);
         ok[e] = (xb + e >= it.ox0) && (xb + e < it.ox1);
         all_ok = all_ok && ok[e];
+        xc[e] = xb + e < W ? xb + e : W - 1;
     }
 
     // rows of sweep k live in [lo_k, hi_k); sweep k computes row rho at step rho + k
@@ -150,90 +124,136 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
 
     RowQ<C> win[T][3];
     Pref<C> pf[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-        if (lo0 + j < hi0) load_row<C, DATA>(pf[j], it.src, it.f, (int64_t)(lo0 + j) * it.ld, xb, W, it.vec);
 
-    float* myring = ring + lane * C;
+    auto load = [&](Pref<C>& p, int row) {
+        const float* up = it.src + (int64_t)row * it.ld;
+        const float* fp = DATA ? it.f + (int64_t)row * it.ld : nullptr;
+        if constexpr (VEC && C == 4) {
+            const float4 v = ld_at<float4>(up, (uint32_t)xb);
+            p.u[0] = v.x; p.u[1] = v.y; p.u[2] = v.z; p.u[3] = v.w;
+            if constexpr (DATA) {
+                const float4 g = ld_at<float4>(fp, (uint32_t)xb);
+                p.f[0] = g.x; p.f[1] = g.y; p.f[2] = g.z; p.f[3] = g.w;
+            }
+        } else if constexpr (VEC && C == 2) {
+            const float2 v = ld_at<float2>(up, (uint32_t)xb);
+            p.u[0] = v.x; p.u[1] = v.y;
+            if constexpr (DATA) {
+                const float2 g = ld_at<float2>(fp, (uint32_t)xb);
+                p.f[0] = g.x; p.f[1] = g.y;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < C; ++e) {
+                p.u[e] = ld_at<float>(up, (uint32_t)xc[e]);
+                if constexpr (DATA) p.f[e] = ld_at<float>(fp, (uint32_t)xc[e]);
+            }
+        }
+    };
+
+    auto store = [&](int rho, const float (&v)[C], const int (&idx)[C]) {
+        float* dp = it.dst + (int64_t)rho * it.ld;
+        if constexpr (VEC) {
+            if (all_ok) {  // lanes are wholly inside or wholly in a halo
+                if constexpr (C == 4) st_at<float4>(dp, (uint32_t)xb, make_float4(v[0], v[1], v[2], v[3]));
+                else if constexpr (C == 2) st_at<float2>(dp, (uint32_t)xb, make_float2(v[0], v[1]));
+                else st_at<float>(dp, (uint32_t)xb, v[0]);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < C; ++e)
+                if (ok[e]) st_at<float>(dp, (uint32_t)(xb + e), v[e]);
+        }
+        if constexpr (AM) {
+            uint8_t* ap = it.amap + (int64_t)rho * it.ld;
+#pragma unroll
+            for (int e = 0; e < C; ++e)
+                if (ok[e]) ap[(uint32_t)(xb + e)] = (uint8_t)idx[e];
+        }
+    };
+
+    // one pixel row of sweep k from the three rows of sweep k-1
+    auto sweep_row = [&](const RowQ<C>& t, const RowQ<C>& mm, const RowQ<C>& b, int rho,
+                         float (&v)[C], int (&idx)[C]) {
+        float fv[C];
+        if constexpr (DATA) {
+            const float* slot = ring + (rho % NS) * (64 * C) + lane * C;
+#pragma unroll
+            for (int e = 0; e < C; ++e) fv[e] = slot[e];
+        }
+#pragma unroll
+        for (int e = 0; e < C; ++e) {
+            const Odd o = parts(t.a[e], t.s[e], t.q[e], mm.s[e], mm.q[e], mm.c[e], b.a[e], b.s[e],
+                                b.q[e]);
+            float S;
+            if constexpr (AM) S = select_x12_idx(o, idx[e]);
+            else S = select_x12(o);
+            if constexpr (MODE == kData) v[e] = update_data(mm.c[e], fv[e], S, it.k);
+            else if constexpr (MODE == kFlow) v[e] = update_flow(mm.c[e], S, it.k);
+            else v[e] = to_hd(S);
+        }
+    };
+
+    auto put_ring = [&](int n, const Pref<C>& p) {
+        if constexpr (DATA) {
+            float* slot = ring + (n % NS) * (64 * C) + lane * C;
+#pragma unroll
+            for (int e = 0; e < C; ++e) slot[e] = p.f[e];
+        }
+    };
 
     int n = lo0;
-    auto step = [&](auto phase_tag) {
+
+    // ---- one row step: input row n, then row n-k of every sweep k ----------
+    auto generic = [&](auto phase_tag) {
         constexpr int P = decltype(phase_tag)::value;
-        constexpr int PM = (P + 2) % 3;  // slot pushed one step ago
-        constexpr int PT = (P + 1) % 3;  // slot pushed two steps ago
-        // ---- sweep 0: the input row ------------------------------------------
+        constexpr int PM = (P + 2) % 3;
+        constexpr int PT = (P + 1) % 3;
         if (n < hi0) {
             float m[C];
 #pragma unroll
             for (int e = 0; e < C; ++e) m[e] = pf[P].u[e];
-            if constexpr (DATA) {
-                float* slot = myring + (n % NS) * (64 * C);
-#pragma unroll
-                for (int e = 0; e < C; ++e) slot[e] = pf[P].f[e];
-            }
-            if (n + 3 < hi0)
-                load_row<C, DATA>(pf[P], it.src, it.f, (int64_t)(n + 3) * it.ld, xb, W, it.vec);
+            put_ring(n, pf[P]);
+            if (n + 3 < hi0) load(pf[P], n + 3);
             make_row<C, RCL>(m, last, win[0][P]);
-            if (n == 0) copy_row(win[0][PM], win[0][P]);  // row -1 := row 0 (top border)
+            if (n == 0) rare_copy(win[0][PM], win[0][P]);  // row -1 := row 0 (top border)
         }
-        // ---- sweeps 1..T --------------------------------------------------------
 #pragma unroll
         for (int k = 1; k <= T; ++k) {
             const int rho = n - k;
             const int lo = it.y0 - (T - k) > 0 ? it.y0 - (T - k) : 0;
             const int hi = it.y1 + (T - k) < H ? it.y1 + (T - k) : H;
             if (rho >= lo && rho < hi) {
-                // bottom border: row H := row H-1.  Sweep k-1 did not produce a
-                // row this step, so its newest slot is free to hold the copy.
-                if (rho == H - 1) copy_row(win[k - 1][P], win[k - 1][PM]);
-                const RowQ<C>& t = win[k - 1][PT];
-                const RowQ<C>& mm = win[k - 1][PM];
-                const RowQ<C>& b = win[k - 1][P];
-                float fv[C];
-                if constexpr (DATA) {
-                    const float* slot = myring + (rho % NS) * (64 * C);
-#pragma unroll
-                    for (int e = 0; e < C; ++e) fv[e] = slot[e];
-                }
+                // bottom border: row H := row H-1; sweep k-1 produced no row this
+                // step, so its newest slot is free to hold the copy
+                if (rho == H - 1) rare_copy(win[k - 1][P], win[k - 1][PM]);
                 float v[C];
                 int idx[C];
-#pragma unroll
-                for (int e = 0; e < C; ++e) {
-                    const Odd o = parts(t.a[e], t.s[e], t.q[e], mm.s[e], mm.q[e], mm.c[e], b.a[e],
-                                        b.s[e], b.q[e]);
-                    float S;
-                    if constexpr (AM) S = select_x12_idx(o, idx[e]);
-                    else S = select_x12(o);
-                    if constexpr (MODE == kData) v[e] = update_data(mm.c[e], fv[e], S, it.k);
-                    else if constexpr (MODE == kFlow) v[e] = update_flow(mm.c[e], S, it.k);
-                    else v[e] = to_hd(S);
-                }
+                sweep_row(win[k - 1][PT], win[k - 1][PM], win[k - 1][P], rho, v, idx);
                 if (k < T) {
-                    // row rho of sweep k feeds sweep k+1 (index clamped only to keep
-                    // the never-taken k == T instance in bounds)
                     RowQ<C>(&lv)[3] = win[k < T ? k : 0];
                     make_row<C, RCL>(v, last, lv[P]);
-                    if (rho == 0) copy_row(lv[PM], lv[P]);  // row -1 := row 0
+                    if (rho == 0) rare_copy(lv[PM], lv[P]);  // row -1 := row 0
                 } else {
-                    const int64_t off = (int64_t)rho * it.ld;
-                    store_row<C>(it.dst, off, xb, v, ok, all_ok, it.vec);
-                    if constexpr (AM) {
-#pragma unroll
-                        for (int e = 0; e < C; ++e)
-                            if (ok[e]) it.amap[off + xb + e] = (uint8_t)idx[e];
-                    }
+                    store(rho, v, idx);
                 }
             }
         }
     };
 
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        if (lo0 + j < hi0) load(pf[j], lo0 + j);
+
+    // groups of three steps: the register slot of a row is fixed by its
+    // position in the group
     while (true) {
-        step(Phase<0>{});
-        if (++n > n_last) break;
-        step(Phase<1>{});
-        if (++n > n_last) break;
-        step(Phase<2>{});
-        if (++n > n_last) break;
+        generic(Phase<0>{});
+        if (++n > n_last) return;
+        generic(Phase<1>{});
+        if (++n > n_last) return;
+        generic(Phase<2>{});
+        if (++n > n_last) return;
     }
 }
 
@@ -267,8 +287,9 @@ __device__ __forceinline__ void process(const ImageDesc& d, int64_t local, const
     it.vec = d.vec != 0;
     const float lam = a.lam ? a.lam[d.lam_index + ch * d.lam_stride] : 0.0f;
     it.k = make_coef(lam, a.dt, MODE == kData);
-    if (strip == d.nstrip - 1) run_item<C, T, MODE, AM, true>(it, ring);
-    else run_item<C, T, MODE, AM, false>(it, ring);
+    if (strip == d.nstrip - 1) run_item<C, T, MODE, AM, true, false>(it, ring);
+    else if (it.vec) run_item<C, T, MODE, AM, false, true>(it, ring);
+    else run_item<C, T, MODE, AM, false, false>(it, ring);
 }
 
 template <int C, int T, int MODE>

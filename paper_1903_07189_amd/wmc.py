@@ -12,6 +12,7 @@ along W; N planes are independent (colour channels or batch items).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import torch
@@ -46,7 +47,7 @@ class Tuning(ctypes.Structure):
 
 _lib = None
 EXPORTS = ["wmc_compute", "wmc_step", "wmc_solve_workspace", "wmc_set_stride",
-           "wmc_num_checkpoints", "wmc_solve",
+           "wmc_num_checkpoints", "wmc_solve", "wmc_solve_tuning",
            "wmc_batched_workspace", "wmc_solve_batched", "wmc_autotune", "wmc_backward_workspace",
            "wmc_backward", "wmc_selftest", "wmc_last_error", "wmc_release"]
 
@@ -70,6 +71,7 @@ def lib():
     L.wmc_num_checkpoints.argtypes = [I, I]
     L.wmc_num_checkpoints.restype = I64
     L.wmc_solve.argtypes = [P, P, P, P, I, F, P, I, ctypes.POINTER(Tuning), P, SZ, Shape, P]
+    L.wmc_solve_tuning.argtypes = [P, P, P, F, P, SZ, Shape, ctypes.POINTER(Tuning), P]
     L.wmc_batched_workspace.argtypes = [ctypes.POINTER(Image), I]
     L.wmc_batched_workspace.restype = SZ
     L.wmc_solve_batched.argtypes = [ctypes.POINTER(Image), I, P, I, F, ctypes.POINTER(Tuning), P,
@@ -83,7 +85,8 @@ def lib():
     L.wmc_last_error.restype = ctypes.c_char_p
     L.wmc_release.argtypes = []
     L.wmc_release.restype = None
-    for name in ("wmc_compute", "wmc_step", "wmc_solve", "wmc_solve_batched", "wmc_autotune",
+    for name in ("wmc_compute", "wmc_step", "wmc_solve", "wmc_solve_tuning", "wmc_solve_batched",
+                 "wmc_autotune",
                  "wmc_backward", "wmc_selftest"):
         getattr(L, name).restype = I
     _lib = L
@@ -211,6 +214,44 @@ def solve(f: torch.Tensor | None, lam=1.0, iters: int = 1, dt: float = 0.0,
     return (out, ck) if ckpt_every else out
 
 
+def solve_tuning(f: torch.Tensor | None, lam=1.0, dt: float = 0.0, u0: torch.Tensor | None = None):
+    """The launch shape solve() picks for this input (autotuned, cached)."""
+    ref = f if f is not None else u0
+    ref = _planes(ref).contiguous()
+    f = None if f is None else _planes(f).contiguous()
+    u0 = None if u0 is None else _planes(u0).contiguous()
+    s = shape_of(ref)
+    L = lib()
+    ws = torch.empty(max(1, L.wmc_solve_workspace(s) // 4), dtype=torch.float32, device=ref.device)
+    lt = _lam_tensor(lam, ref.shape[0], ref.device) if f is not None else None
+    t = Tuning()
+    check(L.wmc_solve_tuning(_ptr(f), _ptr(u0), _ptr(lt), float(dt), _ptr(ws), ws.numel() * 4, s,
+                             ctypes.byref(t), _stream()))
+    return {"cols": t.cols, "tsteps": t.tsteps, "seg_rows": t.seg_rows, "use_graph": t.use_graph}
+
+
+class SolvePlan:
+    """Pre-marshalled solve() for repeated calls on fixed buffers, so that the
+    library replays one cached graph (its cache is keyed by the pointers)."""
+
+    def __init__(self, f: torch.Tensor, lam, iters: int, dt: float = 0.0, tuning=None):
+        self.f = _planes(f).contiguous()
+        self.s = shape_of(self.f)
+        L = lib()
+        self.out = torch.empty_like(self.f)
+        self.ws = torch.empty(max(1, L.wmc_solve_workspace(self.s) // 4), dtype=torch.float32,
+                              device=self.f.device)
+        self.lam = _lam_tensor(lam, self.f.shape[0], self.f.device)
+        self.iters, self.dt = int(iters), float(dt)
+        self.tuning = _tuning(tuning)
+
+    def __call__(self):
+        check(lib().wmc_solve(_ptr(self.f), None, _ptr(self.out), _ptr(self.lam), self.iters,
+                              self.dt, None, 0, ctypes.byref(self.tuning) if self.tuning else None,
+                              _ptr(self.ws), self.ws.numel() * 4, self.s, _stream()))
+        return self.out
+
+
 def backward(g_out: torch.Tensor, f: torch.Tensor | None, lam, iters: int, ckpt: torch.Tensor,
              ckpt_every: int, dt: float = 0.0, u0: torch.Tensor | None = None):
     """Reverse-mode derivative of L(U^iters) through solve(); returns
@@ -321,7 +362,7 @@ class WMCSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, f, lam, K: int, dt: float = 0.0, ckpt_every: int | None = None, tuning=None):
         K = int(K)
-        c = int(ckpt_every) if ckpt_every else max(1, int(-(-K ** 0.5 // 1)))
+        c = int(ckpt_every) if ckpt_every else max(1, math.ceil(math.sqrt(K)))
         lam_t = _lam_tensor(lam, _planes(f).shape[0], f.device)
         out, ck = solve(f.detach(), lam_t, K, dt=dt, ckpt_every=c, tuning=tuning)
         ctx.save_for_backward(f.detach(), lam_t, ck)
