@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the step/batched extras")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-iters", type=int, default=5)
+    ap.add_argument("--tuning", default="",
+                    help="force the launch shape 'cols,tsteps,seg_rows' (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration for rocprofv3)")
     args = ap.parse_args()
@@ -155,7 +157,11 @@ def main():
     f = torch.from_numpy(noisy).to(dev)           # (1, side, side)
     lam = torch.tensor([1.0], device=dev)
 
-    tuning = wmc.solve_tuning(f, lam)             # autotuned once (cached) before timing
+    if args.tuning:
+        c_, t_, r_ = (int(v) for v in args.tuning.split(","))
+        tuning = {"cols": c_, "tsteps": t_, "seg_rows": r_, "use_graph": 1}
+    else:
+        tuning = wmc.solve_tuning(f, lam)         # autotuned once (cached) before timing
     plan = wmc.SolvePlan(f, lam, iters, tuning=tuning)
     for _ in range(args.warmup):
         plan()

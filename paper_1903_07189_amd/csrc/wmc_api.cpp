@@ -160,14 +160,14 @@ void split_run(int len, int T, std::vector<int>& out) {
     }
 }
 
-// Output rows per work item: aim for ~16 waves per CU (memory latency hiding
-// for the single-sweep kernels).
+// Output rows per work item: aim for ~32 waves per CU (memory latency hiding
+// for the single-sweep kernels), at least 8 rows (segment overlap).
 int default_rows(int64_t planes, int64_t h, int64_t w, int C, int T, int ncu) {
     const int64_t strips = strip_count((int)w, C, T);
-    const int64_t target = (int64_t)ncu * 16;
+    const int64_t target = (int64_t)ncu * 32;
     int64_t per_col = std::max<int64_t>(1, target / std::max<int64_t>(1, strips * planes));
     int64_t R = (h + per_col - 1) / per_col;
-    R = std::max<int64_t>(R, 4 * (int64_t)T);
+    R = std::max<int64_t>(R, std::max<int64_t>(8, 4 * (int64_t)T));
     R = std::min<int64_t>(R, 256);
     return (int)std::max<int64_t>(1, std::min<int64_t>(R, h));
 }

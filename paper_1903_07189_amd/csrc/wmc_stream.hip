@@ -125,20 +125,25 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
     RowQ<C> win[T][3];
     Pref<C> pf[3];
 
+    // rows whose f is ever used: those computed by sweep 1 or later
+    const int lo1 = it.y0 - T + 1 > 0 ? it.y0 - T + 1 : 0;
+    const int hi1 = it.y1 + T - 1 < H ? it.y1 + T - 1 : H;
+
     auto load = [&](Pref<C>& p, int row) {
         const float* up = it.src + (int64_t)row * it.ld;
         const float* fp = DATA ? it.f + (int64_t)row * it.ld : nullptr;
+        const bool needf = DATA && row >= lo1 && row < hi1;  // wave-uniform
         if constexpr (VEC && C == 4) {
             const float4 v = ld_at<float4>(up, (uint32_t)xb);
             p.u[0] = v.x; p.u[1] = v.y; p.u[2] = v.z; p.u[3] = v.w;
-            if constexpr (DATA) {
+            if (needf) {
                 const float4 g = ld_at<float4>(fp, (uint32_t)xb);
                 p.f[0] = g.x; p.f[1] = g.y; p.f[2] = g.z; p.f[3] = g.w;
             }
         } else if constexpr (VEC && C == 2) {
             const float2 v = ld_at<float2>(up, (uint32_t)xb);
             p.u[0] = v.x; p.u[1] = v.y;
-            if constexpr (DATA) {
+            if (needf) {
                 const float2 g = ld_at<float2>(fp, (uint32_t)xb);
                 p.f[0] = g.x; p.f[1] = g.y;
             }
@@ -146,7 +151,7 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
 #pragma unroll
             for (int e = 0; e < C; ++e) {
                 p.u[e] = ld_at<float>(up, (uint32_t)xc[e]);
-                if constexpr (DATA) p.f[e] = ld_at<float>(fp, (uint32_t)xc[e]);
+                if (needf) p.f[e] = ld_at<float>(fp, (uint32_t)xc[e]);
             }
         }
     };

@@ -588,3 +588,50 @@ def test_energy_decreases_on_c1(dscale):
     # the denoised result is closer to the clean image than the input
     c = clean[0].astype(np.float64)
     assert np.sqrt(((U - c) ** 2).mean()) < 0.75 * np.sqrt(((f - c) ** 2).mean())
+
+
+# ---------------------------------------------------------------------------------------
+# energies and test helpers: closed forms
+# ---------------------------------------------------------------------------------------
+
+def test_energy_closed_forms():
+    # eq. (wmcr), q = 1: a contrast-J rectangle has sum |H_d| = 2J/3 (four corners)
+    J, lam = 0.5, 3.0
+    U = _rect(12, 13, 3, 9, 4, 10, J)
+    f = U + 0.25
+    data = 0.5 * U.size * 0.25 ** 2
+    assert oracle.energy_wmc(U, f, lam) == pytest.approx(data + lam * 2 * J / 3, rel=1e-14)
+    assert oracle.energy_wmc(U, None, lam) == pytest.approx(lam * 2 * J / 3, rel=1e-14)
+    # eq. (areaReg): constant -> lam * H * W; ramp of slope a along x -> each pixel but
+    # the last column has |grad| = a
+    H, W, a = 5, 8, 0.75
+    assert oracle.energy_area(np.full((H, W), 0.3), None, lam) == pytest.approx(lam * H * W)
+    ramp = np.tile(a * np.arange(W, dtype=np.float64), (H, 1))
+    want = lam * (H * (W - 1) * np.sqrt(1 + a * a) + H)
+    assert oracle.energy_area(ramp, None, lam) == pytest.approx(want, rel=1e-14)
+
+
+def test_near_tie_helpers():
+    """The (2,2) paraboloid pixel is an exact opposite-sign tie; a generic
+    random pixel is not."""
+    H = W = 11
+    c = 5
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    U = (x - c) ** 2 + (y - c) ** 2
+    mask = oracle.near_tie_mask(U, 0.0)
+    assert mask[c + 2, c + 2]
+    assert not mask[c, c] and not mask[c + 1, c]
+    allowed = oracle.allowed_values(U, 0.0)
+    vals = allowed[c + 2, c + 2][~np.isnan(allowed[c + 2, c + 2])]
+    assert set(np.round(vals * 3).astype(int)) == {-4, 4}
+
+
+def test_step_window_equals_full_step():
+    rng = np.random.default_rng(19)
+    U = rng.uniform(0, 1, size=(20, 23))
+    f = rng.uniform(0, 1, size=(20, 23))
+    full = U.copy()
+    for _ in range(3):
+        full = oracle.step(full, f, 1.2)
+    for (y, x) in [(0, 0), (10, 11), (19, 22), (0, 15), (7, 0), (3, 3)]:
+        assert oracle.step_window(U, f, y, x, 3, lam=1.2) == pytest.approx(full[y, x], abs=1e-15)
