@@ -16,6 +16,8 @@ Curvature", arXiv 1903.07189):
   gradient-descent iteration of Sec. 5.2 with A = I (data mode).
 * :func:`energy_wmc` / :func:`energy_area` -- eq. (wmcr) with q = 1 and
   eq. (areaReg), each plus the quadratic data term.
+* :func:`l1_step` / :func:`l1_solve` -- the l1-fidelity primal-dual
+  iteration of Sec. 5.3 (A = I).
 * :func:`listing` -- the Appendix A function's semantics (zero padding, true
   convolution, its candidate order).
 * :func:`step_adjoint` / :func:`solve_adjoint` -- derivative of the update map
@@ -73,6 +75,8 @@ def _load():
         lib.wmco_listing.argtypes = [P, I64, I64, P, P]
         lib.wmco_step_adjoint.argtypes = [P, P, I64, I64, D, D, I, P, P, P, P, P]
         lib.wmco_solve_adjoint.argtypes = [P, P, I64, I64, D, D, I, I, P, P, P, P, P, P]
+        lib.wmco_l1_step.argtypes = [P, P, P, I64, I64, D, D, D, P, P, P]
+        lib.wmco_l1_solve.argtypes = [P, P, P, I64, I64, D, D, D, I, P, P]
         _lib = lib
     return _lib
 
@@ -287,3 +291,39 @@ def step_window(U, f, y: int, x: int, k: int, lam: float = 1.0, delta: float | N
     for _ in range(k):
         u = step(u, ff, lam, delta)
     return float(u[y - y0, x - x0])
+
+
+def l1_default_delta(lam: float, alpha: float) -> float:
+    """Step for the l1 iteration when none is given: 1/(lam + 2/alpha), the
+    largest step for which the update is a convex combination while the dual
+    is unclipped."""
+    return 1.0 / (lam + 2.0 / alpha)
+
+
+def l1_step(U, d, f, lam: float = 1.0, alpha: float = 0.05, delta: float | None = None,
+            return_argmin: bool = False):
+    """One primal-dual step of Sec. 5.3; returns (U', d')."""
+    U, d, f = _d(U), _d(d), _d(f)
+    H, W = U.shape
+    if delta is None:
+        delta = l1_default_delta(lam, alpha)
+    uo, do = np.empty_like(U), np.empty_like(U)
+    m = np.empty((H, W), dtype=np.int8)
+    _load().wmco_l1_step(_p(U), _p(d), _p(f), H, W, float(lam), float(alpha), float(delta),
+                         _p(uo), _p(do), _p(m))
+    return (uo, do, m) if return_argmin else (uo, do)
+
+
+def l1_solve(f, lam: float = 1.0, alpha: float = 0.05, iters: int = 1, delta: float | None = None,
+             u0=None, d0=None):
+    """iters primal-dual steps from (u0 or f, d0 or 0); returns (U, d)."""
+    f = _d(f)
+    H, W = f.shape
+    u0 = None if u0 is None else _d(u0)
+    d0 = None if d0 is None else _d(d0)
+    if delta is None:
+        delta = l1_default_delta(lam, alpha)
+    uo, do = np.empty_like(f), np.empty_like(f)
+    _load().wmco_l1_solve(_p(f), _p(u0), _p(d0), H, W, float(lam), float(alpha), float(delta),
+                          int(iters), _p(uo), _p(do))
+    return uo, do

@@ -30,7 +30,8 @@
  *       is the exact derivative of the piecewise-linear update map with the
  *       selection m held fixed);
  *   O9  "listing mode": the Appendix A function's semantics (true 2-D
- *       convolution, zero padding, its candidate order), for cross-checks.
+ *       convolution, zero padding, its candidate order), for cross-checks;
+ *   O10 the l1-fidelity primal-dual iteration of Sec. 5.3 (A = I).
  *
  * Images are row-major H x W arrays of doubles, x = column, y = row
  * (downwards).  Functions never allocate more than O(H W) scratch.
@@ -320,4 +321,50 @@ void wmco_solve_adjoint(const double* f, const double* u0, int64_t H, int64_t W,
     free(states);
     free(g);
     free(g2);
+}
+
+/* Sec. 5.3: l1 data fidelity min ||U - f||_1 + lam R(U), A = I, solved by the
+ * primal-dual iteration: with r = U^t - f + d^t the dual update is the
+ * clamp d^{t+1} = min(max(r, -alpha), alpha) (b = shrink(r, alpha) eliminated)
+ * and the primal update is
+ *   U^{t+1} = U^t + delta [ lam H_d(U^t) - (2 d^{t+1} - d^t) / alpha ].
+ * Jacobi in U (H_d from U^t only); d is pointwise. */
+void wmco_l1_step(const double* U, const double* d, const double* f, int64_t H, int64_t W,
+                  double lam, double alpha, double delta, double* Uout, double* dout,
+                  int8_t* m_out) {
+    double S[8];
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) {
+            int64_t k = y * W + x;
+            candidates_at(U, H, W, y, x, S);
+            int m = select_first_min(S);
+            double hd = S[m] / 12.0;
+            double r = U[k] - f[k] + d[k];
+            double dn = r > alpha ? alpha : (r < -alpha ? -alpha : r);
+            Uout[k] = U[k] + delta * (lam * hd - (2.0 * dn - d[k]) / alpha);
+            dout[k] = dn;
+            if (m_out) m_out[k] = (int8_t)m;
+        }
+}
+
+/* iters l1 steps from (u0, d0); u0 NULL -> f, d0 NULL -> 0. */
+void wmco_l1_solve(const double* f, const double* u0, const double* d0, int64_t H, int64_t W,
+                   double lam, double alpha, double delta, int iters, double* Uout,
+                   double* dout) {
+    int64_t n = H * W;
+    double* ua = (double*)malloc(sizeof(double) * n);
+    double* ub = (double*)malloc(sizeof(double) * n);
+    double* da = (double*)malloc(sizeof(double) * n);
+    double* db = (double*)malloc(sizeof(double) * n);
+    memcpy(ua, u0 ? u0 : f, sizeof(double) * n);
+    if (d0) memcpy(da, d0, sizeof(double) * n);
+    else memset(da, 0, sizeof(double) * n);
+    for (int t = 0; t < iters; ++t) {
+        wmco_l1_step(ua, da, f, H, W, lam, alpha, delta, ub, db, NULL);
+        double* tu = ua; ua = ub; ub = tu;
+        double* td = da; da = db; db = td;
+    }
+    memcpy(Uout, ua, sizeof(double) * n);
+    memcpy(dout, da, sizeof(double) * n);
+    free(ua); free(ub); free(da); free(db);
 }

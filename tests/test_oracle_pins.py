@@ -635,3 +635,73 @@ def test_step_window_equals_full_step():
         full = oracle.step(full, f, 1.2)
     for (y, x) in [(0, 0), (10, 11), (19, 22), (0, 15), (7, 0), (3, 3)]:
         assert oracle.step_window(U, f, y, x, 3, lam=1.2) == pytest.approx(full[y, x], abs=1e-15)
+
+
+# ---------------------------------------------------------------------------------------
+# the l1-fidelity primal-dual iteration (Sec. 5.3)
+# ---------------------------------------------------------------------------------------
+
+def _shrink(r, a):
+    """Soft threshold: the closed-form b of Sec. 5.3."""
+    return np.where(r > a, r - a, np.where(r < -a, r + a, 0.0))
+
+
+def test_l1_dual_update_matches_shrink_identity():
+    """The dual update d' = clip(r) is the paper's d' = d + U - f - b with
+    b = shrink(r, alpha), r = U - f + d."""
+    rng = np.random.default_rng(30)
+    U = rng.uniform(0, 1, size=(15, 17))
+    f = rng.uniform(0, 1, size=U.shape)
+    d = rng.uniform(-0.1, 0.1, size=U.shape)
+    alpha = 0.07
+    _, dn = oracle.l1_step(U, d, f, 1.0, alpha)
+    r = U - f + d
+    assert np.allclose(dn, d + U - f - _shrink(r, alpha), atol=1e-15)
+    assert np.abs(dn).max() <= alpha
+
+
+def test_l1_fixed_point_and_bounds():
+    U = np.full((9, 11), 0.4)
+    uo, do = oracle.l1_solve(U, lam=2.0, alpha=0.05, iters=20)
+    assert np.array_equal(uo, U) and np.all(do == 0.0)
+    rng = np.random.default_rng(31)
+    f = rng.uniform(0, 1, size=(20, 20))
+    uo, do = oracle.l1_solve(f, lam=1.0, alpha=0.03, iters=30)
+    assert np.abs(do).max() <= 0.03 + 1e-15
+
+
+def test_l1_spike_two_steps_closed_form():
+    """Constant c with one spike c + J, U^0 = f, d^0 = 0.
+    Step 1: r = 0 so d^1 = 0; only the spike moves, by delta lam H_d = -delta lam J
+    (all eight responses equal -12J at the spike, zero at its neighbours).
+    Step 2: at the spike r = -delta lam J, d^2 = clip(r); the spike's own response
+    is -J(1 - delta lam) and its neighbours still see one half window without it."""
+    c, J, lam, alpha = 0.3, 0.5, 1.0, 0.05
+    delta = 1.0 / (lam + 2.0 / alpha)
+    f = np.full((9, 9), c)
+    f[4, 4] += J
+    u1, d1 = oracle.l1_step(f, np.zeros_like(f), f, lam, alpha, delta)
+    assert np.all(d1 == 0.0)
+    want1 = f.copy()
+    want1[4, 4] = c + J - delta * lam * J
+    assert np.allclose(u1, want1, atol=1e-15)
+    u2, d2 = oracle.l1_step(u1, d1, f, lam, alpha, delta)
+    r = -delta * lam * J
+    dn = min(max(r, -alpha), alpha)
+    spike = u1[4, 4] + delta * (lam * (-J * (1 - delta * lam)) - 2 * dn / alpha)
+    assert u2[4, 4] == pytest.approx(spike, abs=1e-15)
+    assert d2[4, 4] == pytest.approx(dn, abs=1e-15)
+    mask = np.ones_like(f, bool)
+    mask[4, 4] = False
+    assert np.allclose(u2[mask], f[mask], atol=1e-15) and np.all(d2[mask] == 0.0)
+
+
+def test_l1_large_alpha_reduces_to_the_flow():
+    """With alpha far above every residual the dual terms vanish and the
+    iteration is the curvature flow of eq. (MCF) with step delta lam."""
+    rng = np.random.default_rng(32)
+    f = rng.uniform(0, 1, size=(14, 16))
+    lam, alpha, delta = 2.0, 1e12, 0.2
+    uo, _ = oracle.l1_solve(f, lam=lam, alpha=alpha, iters=12, delta=delta)
+    flow = oracle.solve(None, iters=12, delta=delta * lam, u0=f)
+    assert np.allclose(uo, flow, atol=1e-9)
