@@ -213,26 +213,32 @@ def main():
 
 def extras(torch, wmc, wmc_synth, f, lam, stream, side):
     ex = {}
-    # plain single-update kernel (one launch per iteration, graph-replayed)
-    t1 = {"cols": 4, "tsteps": 1, "seg_rows": 64, "use_graph": 1}
+    # plain single-update kernel (one launch per iteration, graph-replayed); the
+    # launch shape is picked from a few candidates, best reported
     reps = 50
-    p1 = wmc.SolvePlan(f, lam, reps, tuning=t1)
-    p1()
-    ms = timed(p1, 3, stream, torch) / 3
-    per_launch = ms / reps
-    gbs = BYTES_PER_PX_PASS * side * side / (per_launch * 1e-3) / 1e9
+
+    def t1_gbs(img, side_, iters_, shapes):
+        best = (0.0, None)
+        for c_, r_ in shapes:
+            t1 = {"cols": c_, "tsteps": 1, "seg_rows": r_, "use_graph": 1}
+            p1 = wmc.SolvePlan(img, lam, iters_, tuning=t1)
+            p1()
+            ms = timed(p1, 3, stream, torch) / 3
+            gbs = BYTES_PER_PX_PASS * side_ * side_ / (ms / iters_ * 1e-3) / 1e9
+            if gbs > best[0]:
+                best = (gbs, t1)
+        return best
+
+    gbs, t1 = t1_gbs(f, side, reps, [(2, 16), (2, 32), (4, 8), (4, 32)])
     ex["step_T1_4096"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                          "gpx_per_s": round(side * side / (per_launch * 1e-3) / 1e9, 2),
+                          "gpx_per_s": round(gbs / BYTES_PER_PX_PASS, 2), "tuning": t1,
                           "note": "warm: the 192 MiB working set fits the 256 MB Infinity Cache"}
     # 8192^2 control, larger than the Infinity Cache
     g = torch.rand((1, 8192, 8192), device=f.device)
-    p2 = wmc.SolvePlan(g, lam, 20, tuning=t1)
-    p2()
-    ms = timed(p2, 2, stream, torch) / 2
-    per_launch = ms / 20
-    gbs = BYTES_PER_PX_PASS * 8192 * 8192 / (per_launch * 1e-3) / 1e9
-    ex["step_T1_8192"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
-    del g, p2
+    gbs, t1 = t1_gbs(g, 8192, 20, [(4, 4), (4, 8), (2, 4)])
+    ex["step_T1_8192"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                          "tuning": t1}
+    del g
     # operator alone (read U, write H)
     h = wmc.compute(f)
     ms = timed(lambda: wmc.compute(f), 20, stream, torch) / 20

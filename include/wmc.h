@@ -136,6 +136,25 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
 int wmc_solve_tuning(const float* f, const float* u0, const float* lam, float dt, void* ws,
                      size_t ws_bytes, wmc_shape s, wmc_tuning* out, void* stream);
 
+/* Bytes of workspace wmc_solve_l1 needs (two extra plane sets). */
+size_t wmc_l1_workspace(wmc_shape s);
+
+/* ---------------------------------------------------------------------------
+ * wmc_solve_l1 -- the l1-fidelity model min ||U - f||_1 + lam R_area(U) of
+ * Sec. 5.3 (A = I) by its primal-dual iteration, fused and temporally blocked
+ * like wmc_solve.  Per step, with r = U - f + d:
+ *   d' = clamp(r, -alpha, alpha)          (the shrinkage b is eliminated)
+ *   U' = U + dt [ lam H_d(U) - (2 d' - d) / alpha ]
+ * dt <= 0 selects 1/(lam + 2/alpha), the largest step for which the update is
+ * a convex combination while the dual is unclipped.  u0 NULL -> f, d0 NULL ->
+ * 0.  Outputs: u_out = U^iters, d_out = d^iters (layout s).  lam: device
+ * array of s.n values; alpha > 0.  ws: wmc_l1_workspace(s) bytes.
+ * Outputs must not overlap inputs, each other or ws.  20 B/pixel per pass.
+ * ------------------------------------------------------------------------- */
+int wmc_solve_l1(const float* f, const float* u0, const float* d0, float* u_out, float* d_out,
+                 const float* lam, float alpha, int iters, float dt, const wmc_tuning* tune,
+                 void* ws, size_t ws_bytes, wmc_shape s, void* stream);
+
 /* Bytes of workspace wmc_solve_batched needs for this batch. */
 size_t wmc_batched_workspace(const wmc_image* imgs, int n_imgs);
 

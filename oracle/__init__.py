@@ -75,7 +75,7 @@ def _load():
         lib.wmco_listing.argtypes = [P, I64, I64, P, P]
         lib.wmco_step_adjoint.argtypes = [P, P, I64, I64, D, D, I, P, P, P, P, P]
         lib.wmco_solve_adjoint.argtypes = [P, P, I64, I64, D, D, I, I, P, P, P, P, P, P]
-        lib.wmco_l1_step.argtypes = [P, P, P, I64, I64, D, D, D, P, P, P]
+        lib.wmco_l1_step.argtypes = [P, P, P, I64, I64, D, D, D, P, P, P, P]
         lib.wmco_l1_solve.argtypes = [P, P, P, I64, I64, D, D, D, I, P, P]
         _lib = lib
     return _lib
@@ -301,16 +301,18 @@ def l1_default_delta(lam: float, alpha: float) -> float:
 
 
 def l1_step(U, d, f, lam: float = 1.0, alpha: float = 0.05, delta: float | None = None,
-            return_argmin: bool = False):
-    """One primal-dual step of Sec. 5.3; returns (U', d')."""
+            m_forced=None, return_argmin: bool = False):
+    """One primal-dual step of Sec. 5.3; returns (U', d').  m_forced replays a
+    selection as in :func:`step`."""
     U, d, f = _d(U), _d(d), _d(f)
     H, W = U.shape
     if delta is None:
         delta = l1_default_delta(lam, alpha)
+    mf = _m8(m_forced, (H, W))
     uo, do = np.empty_like(U), np.empty_like(U)
     m = np.empty((H, W), dtype=np.int8)
     _load().wmco_l1_step(_p(U), _p(d), _p(f), H, W, float(lam), float(alpha), float(delta),
-                         _p(uo), _p(do), _p(m))
+                         _p(mf), _p(uo), _p(do), _p(m))
     return (uo, do, m) if return_argmin else (uo, do)
 
 

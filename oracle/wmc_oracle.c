@@ -328,16 +328,17 @@ void wmco_solve_adjoint(const double* f, const double* u0, int64_t H, int64_t W,
  * clamp d^{t+1} = min(max(r, -alpha), alpha) (b = shrink(r, alpha) eliminated)
  * and the primal update is
  *   U^{t+1} = U^t + delta [ lam H_d(U^t) - (2 d^{t+1} - d^t) / alpha ].
- * Jacobi in U (H_d from U^t only); d is pointwise. */
+ * Jacobi in U (H_d from U^t only); d is pointwise.  m_forced as in
+ * wmco_step. */
 void wmco_l1_step(const double* U, const double* d, const double* f, int64_t H, int64_t W,
-                  double lam, double alpha, double delta, double* Uout, double* dout,
-                  int8_t* m_out) {
+                  double lam, double alpha, double delta, const int8_t* m_forced, double* Uout,
+                  double* dout, int8_t* m_out) {
     double S[8];
     for (int64_t y = 0; y < H; ++y)
         for (int64_t x = 0; x < W; ++x) {
             int64_t k = y * W + x;
             candidates_at(U, H, W, y, x, S);
-            int m = select_first_min(S);
+            int m = (m_forced && m_forced[k] >= 0) ? m_forced[k] : select_first_min(S);
             double hd = S[m] / 12.0;
             double r = U[k] - f[k] + d[k];
             double dn = r > alpha ? alpha : (r < -alpha ? -alpha : r);
@@ -360,7 +361,7 @@ void wmco_l1_solve(const double* f, const double* u0, const double* d0, int64_t 
     if (d0) memcpy(da, d0, sizeof(double) * n);
     else memset(da, 0, sizeof(double) * n);
     for (int t = 0; t < iters; ++t) {
-        wmco_l1_step(ua, da, f, H, W, lam, alpha, delta, ub, db, NULL);
+        wmco_l1_step(ua, da, f, H, W, lam, alpha, delta, NULL, ub, db, NULL);
         double* tu = ua; ua = ub; ub = tu;
         double* td = da; da = db; db = td;
     }

@@ -6,8 +6,9 @@ gfx950 behind the C ABI of include/wmc.h (libwmc.so).  This package is the
 thin Python binding of that ABI; see :mod:`paper_1903_07189_amd.wmc`.
 """
 from .wmc import (WMCError, WMCSolve, SolveBatchedPlan, SolvePlan, autotune, backward, compute,
-                  lib, release, selftest, shape_of, solve, solve_batched, solve_tuning, step)
+                  lib, release, selftest, shape_of, solve, solve_batched, solve_l1, solve_tuning,
+                  step)
 
 __all__ = ["WMCError", "WMCSolve", "SolveBatchedPlan", "SolvePlan", "autotune", "backward",
            "compute", "lib", "release", "selftest", "shape_of", "solve", "solve_batched",
-           "solve_tuning", "step"]
+           "solve_l1", "solve_tuning", "step"]

@@ -553,6 +553,35 @@ int enqueue_single(const wmc_shape& s, const float* src, const float* f, float* 
     return WMC_OK;
 }
 
+// One launch of `sweeps` fused l1 primal-dual sweeps (Sec. 5.3).
+int enqueue_l1(const wmc_shape& s, const float* src, const float* dsrc, const float* f,
+               float* dst, float* ddst, const float* lam, float alpha, float dt, int C, int T,
+               int R, hipStream_t st) {
+    const bool vec = vec_cols({src, f, dst}, s.ld, s.n > 1 ? s.ps : 0) >= C;
+    ImageDesc d{};
+    d.src0 = src;
+    d.f = f;
+    d.bufA = dst;
+    d.bufB = dst;
+    d.dsrc0 = dsrc;
+    d.dA = ddst;
+    d.dB = ddst;
+    d.ld = s.ld;
+    d.ps = s.ps;
+    d.H = (int32_t)s.h;
+    d.W = (int32_t)s.w;
+    d.channels = (int32_t)s.n;
+    d.lam_index = 0;
+    d.lam_stride = 1;
+    d.nstrip = strip_count((int)s.w, C, T);
+    d.nseg = seg_count((int)s.h, R);
+    d.vec = vec ? 1 : 0;
+    LaunchArgs a{lam, dt, 0, 1, R, alpha};
+    const hipError_t e = launch_stream_single(C, T, kModeL1, false, d, a, st);
+    if (e != hipSuccess) return hip_fail(e, "launch of the l1 streaming kernel");
+    return WMC_OK;
+}
+
 // ---------------------------------------------------------------------------
 // autotuner
 // ---------------------------------------------------------------------------
@@ -935,6 +964,114 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
     key_add(key, dt);
     key_add(key, ckpt);
     key_add(key, ckpt_every);
+    key_add(key, ws);
+    key_add(key, t);
+    key_add(key, dev);
+    auto prepare = [](PlanEntry&) { return WMC_OK; };
+    return run_plan(key, dev, st, true, prepare, enqueue);
+}
+
+size_t wmc_l1_workspace(wmc_shape s) {
+    if (check_shape(s)) return 0;
+    return 2 * (size_t)set_stride_elems(s) * sizeof(float);
+}
+
+int wmc_solve_l1(const float* f, const float* u0, const float* d0, float* u_out, float* d_out,
+                 const float* lam, float alpha, int iters, float dt, const wmc_tuning* tune,
+                 void* ws, size_t ws_bytes, wmc_shape s, void* stream) {
+    g_err.clear();
+    int rc = check_shape(s);
+    if (rc) return rc;
+    if (!f || !lam || !u_out || !d_out)
+        return fail(WMC_EINVAL, "wmc_solve_l1: f, lam, u_out and d_out are required");
+    if (!(alpha > 0.0f) || !std::isfinite(alpha)) return fail(WMC_EINVAL, "wmc_solve_l1: alpha must be > 0");
+    if (iters < 0) return fail(WMC_EINVAL, "wmc_solve_l1: iters must be >= 0");
+    if (!std::isfinite(dt)) return fail(WMC_EINVAL, "wmc_solve_l1: dt must be finite");
+    const int64_t ext = extent_elems(s);
+    const int64_t set = set_stride_elems(s);
+    if (iters >= 2 && (!ws || ws_bytes < wmc_l1_workspace(s)))
+        return fail(WMC_ENOMEM, "wmc_solve_l1: workspace smaller than wmc_l1_workspace()");
+    const float* src0 = u0 ? u0 : f;
+    float* wsU = static_cast<float*>(ws);
+    float* wsD = ws ? static_cast<float*>(ws) + set : nullptr;
+    const Range ro = range_of(u_out, ext, 4), rd = range_of(d_out, ext, 4);
+    const Range rw = range_of(iters >= 2 ? ws : nullptr, 2 * set, 4);
+    for (const Range& in : {range_of(f, ext, 4), range_of(u0, ext, 4), range_of(d0, ext, 4)})
+        if (overlaps(ro, in) || overlaps(rd, in) || overlaps(rw, in))
+            return fail(WMC_EINVAL, "wmc_solve_l1: an output or ws overlaps an input");
+    if (overlaps(ro, rd) || overlaps(ro, rw) || overlaps(rd, rw))
+        return fail(WMC_EINVAL, "wmc_solve_l1: outputs overlap each other or ws");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t st = as_stream(stream);
+    if (iters == 0) {
+        hipError_t e = launch_copy_planes(src0, u_out, s.n, s.h, s.w, s.ld, s.ps, st);
+        if (e == hipSuccess) {
+            if (d0) e = launch_copy_planes(d0, d_out, s.n, s.h, s.w, s.ld, s.ps, st);
+            else e = launch_fill_f32(d_out, ext, 0.0f, st);
+        }
+        return e == hipSuccess ? WMC_OK : hip_fail(e, "copy");
+    }
+    Tuned t{};
+    bool graph = true;
+    if (tuning_complete(tune)) {
+        rc = resolve_tuning(tune, Tuned{2, 3, 16}, &t, &graph);
+    } else {
+        const Tuned deflt{std::min(2, vec_cols({src0, f, u_out}, s.ld, s.n > 1 ? s.ps : 0)), 3,
+                          default_rows(s.n, s.h, s.w, 2, 3, num_cu(dev))};
+        std::ostringstream k;
+        k << arch_name(dev) << "|single|l1|h" << ilog2_ceil(s.h) << "|w" << ilog2_ceil(s.w) << "|n"
+          << ilog2_ceil(s.n);
+        auto search = [&](Tuned* out) {
+            float* scratchU = iters >= 2 ? wsU : u_out;
+            float* scratchD = iters >= 2 ? wsD : d_out;
+            auto run = [&](int C, int T, int R, hipStream_t ss) {
+                return enqueue_l1(s, src0, d0, f, scratchU, scratchD, lam, alpha, dt, C, T, R, ss);
+            };
+            return tune_search(run, s.h, st, out);
+        };
+        Tuned auto_t{};
+        rc = get_tuning(k.str(), deflt, search, &auto_t);
+        if (rc) return rc;
+        rc = resolve_tuning(tune, auto_t, &t, &graph);
+    }
+    if (rc) return rc;
+    // launch depths and the (U, d) buffer pair each launch writes: the last
+    // writes the outputs, consecutive launches alternate with the workspace
+    std::vector<int> depth;
+    split_run(iters, t.T, depth);
+    const int L = (int)depth.size();
+    std::vector<int> to_out(L);
+    for (int l = L - 1; l >= 0; --l) to_out[l] = (l == L - 1) ? 1 : !to_out[l + 1];
+    auto enqueue = [&](hipStream_t ss, PlanEntry&) -> int {
+        const float* su = src0;
+        const float* sd = d0;
+        for (int l = 0; l < L; ++l) {
+            float* du = to_out[l] ? u_out : wsU;
+            float* dd = to_out[l] ? d_out : wsD;
+            const int r = enqueue_l1(s, su, sd, f, du, dd, lam, alpha, dt, t.C, depth[l], t.R, ss);
+            if (r) return r;
+            su = du;
+            sd = dd;
+        }
+        return WMC_OK;
+    };
+    if (!graph) {
+        PlanEntry scratch;
+        return enqueue(st, scratch);
+    }
+    std::string key = "l1|";
+    key_add(key, s);
+    key_add(key, f);
+    key_add(key, u0);
+    key_add(key, d0);
+    key_add(key, u_out);
+    key_add(key, d_out);
+    key_add(key, lam);
+    key_add(key, alpha);
+    key_add(key, iters);
+    key_add(key, dt);
     key_add(key, ws);
     key_add(key, t);
     key_add(key, dev);

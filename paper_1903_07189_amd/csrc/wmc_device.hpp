@@ -47,10 +47,11 @@ __device__ __forceinline__ float from_upper_lane(float old, float src) {
                                                       0x130, 0xF, 0xF, false));
 }
 
-// Per-row quantities of C consecutive columns held by one lane.
+// Per-row quantities of C consecutive columns held by one lane; d is the
+// dual variable of the l1 iteration (unused by the other modes).
 template <int C>
 struct RowQ {
-    float a[C], s[C], q[C], c[C];
+    float a[C], s[C], q[C], c[C], d[C];
 };
 
 // Builds the row quantities from the lane's C centre values.  The outer
@@ -128,13 +129,15 @@ __device__ __forceinline__ float select_x12_idx(const Odd& o, int& idx) {
 }
 
 // Output modes of the streaming kernel.
-enum Mode : int { kCompute = 0, kData = 1, kFlow = 2 };
+enum Mode : int { kCompute = 0, kData = 1, kFlow = 2, kL1 = 3 };
 
 // Per-plane coefficients of the update.
 struct Coef {
     float delta;   // step size
-    float lam12;   // lam / 12 (data mode)
+    float lam12;   // lam / 12 (data and l1 modes)
     float delta12; // delta / 12 (flow mode)
+    float alpha;   // dual bound (l1 mode)
+    float ainv;    // 1 / alpha (l1 mode)
 };
 
 // U' = U + delta ((f - U) + lam H_d), H_d = S / 12.
@@ -147,6 +150,16 @@ __device__ __forceinline__ float update_flow(float c, float S, const Coef& k) {
     return __builtin_fmaf(k.delta12, S, c);
 }
 
+// l1 fidelity (Sec. 5.3): r = U - f + d, d' = clamp(r, -alpha, alpha),
+// U' = U + delta (lam H_d - (2 d' - d) / alpha).  Returns U', writes d'.
+__device__ __forceinline__ float update_l1(float c, float f, float d, float S, const Coef& k,
+                                           float& dn) {
+    const float r = (c - f) + d;
+    dn = __builtin_amdgcn_fmed3f(r, -k.alpha, k.alpha);
+    const float t = __builtin_fmaf(2.0f, dn, -d);
+    return __builtin_fmaf(k.delta, __builtin_fmaf(k.lam12, S, -k.ainv * t), c);
+}
+
 __device__ __forceinline__ float to_hd(float S) { return S * (1.0f / 12.0f); }
 
 // Resolves the step size for one plane: dt > 0 as given, otherwise
@@ -154,6 +167,20 @@ __device__ __forceinline__ float to_hd(float S) { return S * (1.0f / 12.0f); }
 __device__ __forceinline__ Coef make_coef(float lam, float dt, bool data) {
     Coef k;
     k.delta = dt > 0.0f ? dt : (data ? 1.0f / (1.0f + lam) : 1.0f);
+    k.lam12 = lam / 12.0f;
+    k.delta12 = k.delta / 12.0f;
+    k.alpha = 0.0f;
+    k.ainv = 0.0f;
+    return k;
+}
+
+// l1 mode: dt > 0 as given, otherwise 1/(lam + 2/alpha), the largest step
+// for which the update is a convex combination while the dual is unclipped.
+__device__ __forceinline__ Coef make_coef_l1(float lam, float dt, float alpha) {
+    Coef k;
+    k.alpha = alpha;
+    k.ainv = 1.0f / alpha;
+    k.delta = dt > 0.0f ? dt : 1.0f / (lam + 2.0f / alpha);
     k.lam12 = lam / 12.0f;
     k.delta12 = k.delta / 12.0f;
     return k;

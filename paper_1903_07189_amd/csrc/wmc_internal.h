@@ -40,6 +40,9 @@ struct ImageDesc {
     float* bufA;        // selectable buffers (dst_sel/src_sel 1 and 2)
     float* bufB;
     uint8_t* amap;      // selection map (argmin variant only)
+    const float* dsrc0; // l1 mode: dual state read with src_sel == 0 (null: zero)
+    float* dA;          // l1 mode: dual buffers paired with bufA / bufB
+    float* dB;
     int64_t ld, ps;     // row / plane stride, elements
     int32_t H, W;
     int32_t channels;
@@ -56,9 +59,10 @@ struct LaunchArgs {
     int32_t src_sel;   // 0: src0, 1: bufA, 2: bufB
     int32_t dst_sel;   // 1: bufA, 2: bufB
     int32_t R;         // output rows per work item
+    float alpha;       // l1 mode: dual bound
 };
 
-enum { kModeCompute = 0, kModeData = 1, kModeFlow = 2 };
+enum { kModeCompute = 0, kModeData = 1, kModeFlow = 2, kModeL1 = 3 };
 
 // Host-side launchers (wmc_stream.hip).  Return a hipError_t.
 bool stream_variant_exists(int C, int T, int mode, bool argmin);

@@ -39,6 +39,7 @@ template <int C>
 struct Pref {
     float u[C];
     float f[C];
+    float d[C];  // l1 mode: dual state of the input row
 };
 
 template <int C>
@@ -49,6 +50,7 @@ __device__ __forceinline__ void copy_row(RowQ<C>& d, const RowQ<C>& s) {
         d.s[e] = s.s[e];
         d.q[e] = s.q[e];
         d.c[e] = s.c[e];
+        d.d[e] = s.d[e];
     }
 }
 
@@ -71,6 +73,8 @@ struct Item {
     const float* src;
     const float* f;
     float* dst;
+    const float* dsrc;  // l1 mode: dual state in (null: zero)
+    float* ddst;        // l1 mode: dual state out
     uint8_t* amap;
     int64_t ld;
     int H, W;
@@ -99,7 +103,8 @@ __device__ __forceinline__ void st_at(float* row, uint32_t col, V v) {
 // vector access.
 template <int C, int T, int MODE, bool AM, bool RCL, bool VEC>
 __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring) {
-    constexpr bool DATA = (MODE == kData);
+    constexpr bool L1 = (MODE == kL1);
+    constexpr bool DATA = (MODE == kData) || L1;  // modes that read f
     constexpr int NS = T + 1;  // f ring slots
     const int lane = threadIdx.x & 63;
     const int xb = it.x0 + C * lane;
@@ -133,6 +138,16 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
         const float* up = it.src + (int64_t)row * it.ld;
         const float* fp = DATA ? it.f + (int64_t)row * it.ld : nullptr;
         const bool needf = DATA && row >= lo1 && row < hi1;  // wave-uniform
+        if constexpr (L1) {
+            if (needf && it.dsrc) {
+                const float* dp = it.dsrc + (int64_t)row * it.ld;
+#pragma unroll
+                for (int e = 0; e < C; ++e) p.d[e] = ld_at<float>(dp, (uint32_t)xc[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < C; ++e) p.d[e] = 0.0f;
+            }
+        }
         if constexpr (VEC && C == 4) {
             const float4 v = ld_at<float4>(up, (uint32_t)xb);
             p.u[0] = v.x; p.u[1] = v.y; p.u[2] = v.z; p.u[3] = v.w;
@@ -156,7 +171,13 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
         }
     };
 
-    auto store = [&](int rho, const float (&v)[C], const int (&idx)[C]) {
+    auto store = [&](int rho, const float (&v)[C], const int (&idx)[C], const float (&dv)[C]) {
+        if constexpr (L1) {
+            float* qp = it.ddst + (int64_t)rho * it.ld;
+#pragma unroll
+            for (int e = 0; e < C; ++e)
+                if (ok[e]) st_at<float>(qp, (uint32_t)(xb + e), dv[e]);
+        }
         float* dp = it.dst + (int64_t)rho * it.ld;
         if constexpr (VEC) {
             if (all_ok) {  // lanes are wholly inside or wholly in a halo
@@ -179,7 +200,7 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
 
     // one pixel row of sweep k from the three rows of sweep k-1
     auto sweep_row = [&](const RowQ<C>& t, const RowQ<C>& mm, const RowQ<C>& b, int rho,
-                         float (&v)[C], int (&idx)[C]) {
+                         float (&v)[C], int (&idx)[C], float (&dv)[C]) {
         float fv[C];
         if constexpr (DATA) {
             const float* slot = ring + (rho % NS) * (64 * C) + lane * C;
@@ -193,7 +214,8 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
             float S;
             if constexpr (AM) S = select_x12_idx(o, idx[e]);
             else S = select_x12(o);
-            if constexpr (MODE == kData) v[e] = update_data(mm.c[e], fv[e], S, it.k);
+            if constexpr (L1) v[e] = update_l1(mm.c[e], fv[e], mm.d[e], S, it.k, dv[e]);
+            else if constexpr (MODE == kData) v[e] = update_data(mm.c[e], fv[e], S, it.k);
             else if constexpr (MODE == kFlow) v[e] = update_flow(mm.c[e], S, it.k);
             else v[e] = to_hd(S);
         }
@@ -215,12 +237,20 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
         constexpr int PM = (P + 2) % 3;
         constexpr int PT = (P + 1) % 3;
         if (n < hi0) {
-            float m[C];
+            // take row n out of its prefetch slot before the slot is refilled
+            float m[C], dm[C];
 #pragma unroll
-            for (int e = 0; e < C; ++e) m[e] = pf[P].u[e];
+            for (int e = 0; e < C; ++e) {
+                m[e] = pf[P].u[e];
+                dm[e] = L1 ? pf[P].d[e] : 0.0f;
+            }
             put_ring(n, pf[P]);
             if (n + 3 < hi0) load(pf[P], n + 3);
             make_row<C, RCL>(m, last, win[0][P]);
+            if constexpr (L1) {
+#pragma unroll
+                for (int e = 0; e < C; ++e) win[0][P].d[e] = dm[e];
+            }
             if (n == 0) rare_copy(win[0][PM], win[0][P]);  // row -1 := row 0 (top border)
         }
 #pragma unroll
@@ -232,15 +262,19 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
                 // bottom border: row H := row H-1; sweep k-1 produced no row this
                 // step, so its newest slot is free to hold the copy
                 if (rho == H - 1) rare_copy(win[k - 1][P], win[k - 1][PM]);
-                float v[C];
+                float v[C], dv[C];
                 int idx[C];
-                sweep_row(win[k - 1][PT], win[k - 1][PM], win[k - 1][P], rho, v, idx);
+                sweep_row(win[k - 1][PT], win[k - 1][PM], win[k - 1][P], rho, v, idx, dv);
                 if (k < T) {
                     RowQ<C>(&lv)[3] = win[k < T ? k : 0];
                     make_row<C, RCL>(v, last, lv[P]);
+                    if constexpr (L1) {
+#pragma unroll
+                        for (int e = 0; e < C; ++e) lv[P].d[e] = dv[e];
+                    }
                     if (rho == 0) rare_copy(lv[PM], lv[P]);  // row -1 := row 0
                 } else {
-                    store(rho, v, idx);
+                    store(rho, v, idx, dv);
                 }
             }
         }
@@ -280,6 +314,15 @@ __device__ __forceinline__ void process(const ImageDesc& d, int64_t local, const
     it.f = d.f ? d.f + poff : nullptr;
     it.dst = dstb + poff;
     it.amap = d.amap ? d.amap + poff : nullptr;
+    if constexpr (MODE == kL1) {
+        // l1 launches are single plane sets with the dual read from dsrc0 and
+        // written to dA (the host passes explicit pointers per launch)
+        it.dsrc = d.dsrc0 ? d.dsrc0 + poff : nullptr;
+        it.ddst = d.dA + poff;
+    } else {
+        it.dsrc = nullptr;
+        it.ddst = nullptr;
+    }
     it.ld = d.ld;
     it.H = d.H;
     it.W = d.W;
@@ -291,7 +334,8 @@ __device__ __forceinline__ void process(const ImageDesc& d, int64_t local, const
     it.y1 = it.y0 + a.R < d.H ? it.y0 + a.R : d.H;
     it.vec = d.vec != 0;
     const float lam = a.lam ? a.lam[d.lam_index + ch * d.lam_stride] : 0.0f;
-    it.k = make_coef(lam, a.dt, MODE == kData);
+    if constexpr (MODE == kL1) it.k = make_coef_l1(lam, a.dt, a.alpha);
+    else it.k = make_coef(lam, a.dt, MODE == kData);
     if (strip == d.nstrip - 1) run_item<C, T, MODE, AM, true, false>(it, ring);
     else if (it.vec) run_item<C, T, MODE, AM, false, true>(it, ring);
     else run_item<C, T, MODE, AM, false, false>(it, ring);
@@ -299,7 +343,7 @@ __device__ __forceinline__ void process(const ImageDesc& d, int64_t local, const
 
 template <int C, int T, int MODE>
 constexpr int ring_floats() {
-    return MODE == kData ? kWavesPerBlock * (T + 1) * 64 * C : 1;
+    return (MODE == kData || MODE == kL1) ? kWavesPerBlock * (T + 1) * 64 * C : 1;
 }
 
 template <int C, int T, int MODE, bool AM>
@@ -311,7 +355,8 @@ __global__ __launch_bounds__(kBlock) void k_stream_single(ImageDesc d, LaunchArg
     const int64_t total = (int64_t)d.channels * d.nseg * d.nstrip;
     const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
     if (item >= total) return;
-    process<C, T, MODE, AM>(d, item, a, ring + (MODE == kData ? wv * (T + 1) * 64 * C : 0));
+    process<C, T, MODE, AM>(d, item, a,
+                            ring + ((MODE == kData || MODE == kL1) ? wv * (T + 1) * 64 * C : 0));
 }
 
 // Persistent variant: a fixed grid of waves pulls work items of all images
@@ -434,6 +479,12 @@ static SingleFn single_table(int C, int T, int mode, bool am) {
     static const SingleFn flow_tab[3][6] = {{WMC_T_LIST(WMC_S, 1, kFlow)},
                                             {WMC_T_LIST(WMC_S, 2, kFlow)},
                                             {WMC_T_LIST(WMC_S, 4, kFlow)}};
+    if (mode == kModeL1) {
+        static const SingleFn l1_tab[3][6] = {{WMC_T_LIST(WMC_S, 1, kL1)},
+                                              {WMC_T_LIST(WMC_S, 2, kL1)},
+                                              {WMC_T_LIST(WMC_S, 4, kL1)}};
+        return l1_tab[ci][ti];
+    }
 #undef WMC_S
     return mode == kModeData ? data_tab[ci][ti] : flow_tab[ci][ti];
 }

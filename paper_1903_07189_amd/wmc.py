@@ -47,7 +47,8 @@ class Tuning(ctypes.Structure):
 
 _lib = None
 EXPORTS = ["wmc_compute", "wmc_step", "wmc_solve_workspace", "wmc_set_stride",
-           "wmc_num_checkpoints", "wmc_solve", "wmc_solve_tuning",
+           "wmc_num_checkpoints", "wmc_solve", "wmc_solve_tuning", "wmc_l1_workspace",
+           "wmc_solve_l1",
            "wmc_batched_workspace", "wmc_solve_batched", "wmc_autotune", "wmc_backward_workspace",
            "wmc_backward", "wmc_selftest", "wmc_last_error", "wmc_release"]
 
@@ -72,6 +73,9 @@ def lib():
     L.wmc_num_checkpoints.restype = I64
     L.wmc_solve.argtypes = [P, P, P, P, I, F, P, I, ctypes.POINTER(Tuning), P, SZ, Shape, P]
     L.wmc_solve_tuning.argtypes = [P, P, P, F, P, SZ, Shape, ctypes.POINTER(Tuning), P]
+    L.wmc_l1_workspace.argtypes = [Shape]
+    L.wmc_l1_workspace.restype = SZ
+    L.wmc_solve_l1.argtypes = [P, P, P, P, P, P, F, I, F, ctypes.POINTER(Tuning), P, SZ, Shape, P]
     L.wmc_batched_workspace.argtypes = [ctypes.POINTER(Image), I]
     L.wmc_batched_workspace.restype = SZ
     L.wmc_solve_batched.argtypes = [ctypes.POINTER(Image), I, P, I, F, ctypes.POINTER(Tuning), P,
@@ -85,7 +89,8 @@ def lib():
     L.wmc_last_error.restype = ctypes.c_char_p
     L.wmc_release.argtypes = []
     L.wmc_release.restype = None
-    for name in ("wmc_compute", "wmc_step", "wmc_solve", "wmc_solve_tuning", "wmc_solve_batched",
+    for name in ("wmc_compute", "wmc_step", "wmc_solve", "wmc_solve_tuning", "wmc_solve_l1",
+                 "wmc_solve_batched",
                  "wmc_autotune",
                  "wmc_backward", "wmc_selftest"):
         getattr(L, name).restype = I
@@ -212,6 +217,27 @@ def solve(f: torch.Tensor | None, lam=1.0, iters: int = 1, dt: float = 0.0,
     if squeeze:
         out = out[0]
     return (out, ck) if ckpt_every else out
+
+
+def solve_l1(f: torch.Tensor, lam=1.0, alpha: float = 0.05, iters: int = 1, dt: float = 0.0,
+             u0: torch.Tensor | None = None, d0: torch.Tensor | None = None, tuning=None):
+    """The l1-fidelity primal-dual iteration of Sec. 5.3; returns (U, d)."""
+    squeeze = f.dim() == 2
+    f = _planes(f).contiguous()
+    u0 = None if u0 is None else _planes(u0).contiguous()
+    d0 = None if d0 is None else _planes(d0).contiguous()
+    s = shape_of(f)
+    L = lib()
+    out, dout = torch.empty_like(f), torch.empty_like(f)
+    ws = torch.empty(max(1, L.wmc_l1_workspace(s) // 4), dtype=torch.float32, device=f.device)
+    lt = _lam_tensor(lam, f.shape[0], f.device)
+    tn = _tuning(tuning)
+    check(L.wmc_solve_l1(_ptr(f), _ptr(u0), _ptr(d0), _ptr(out), _ptr(dout), _ptr(lt),
+                         float(alpha), int(iters), float(dt), ctypes.byref(tn) if tn else None,
+                         _ptr(ws), ws.numel() * 4, s, _stream()))
+    if squeeze:
+        return out[0], dout[0]
+    return out, dout
 
 
 def solve_tuning(f: torch.Tensor | None, lam=1.0, dt: float = 0.0, u0: torch.Tensor | None = None):
