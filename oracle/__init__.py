@@ -18,6 +18,8 @@ Curvature", arXiv 1903.07189):
   eq. (areaReg), each plus the quadratic data term.
 * :func:`l1_step` / :func:`l1_solve` -- the l1-fidelity primal-dual
   iteration of Sec. 5.3 (A = I).
+* :func:`fd_compute` / :func:`fd_flow` -- the conventional finite-difference
+  discretisation of eq. (rhs) and its curvature flow (Sec. 5.4 comparator).
 * :func:`listing` -- the Appendix A function's semantics (zero padding, true
   convolution, its candidate order).
 * :func:`step_adjoint` / :func:`solve_adjoint` -- derivative of the update map
@@ -77,6 +79,8 @@ def _load():
         lib.wmco_solve_adjoint.argtypes = [P, P, I64, I64, D, D, I, I, P, P, P, P, P, P]
         lib.wmco_l1_step.argtypes = [P, P, P, I64, I64, D, D, D, P, P, P, P]
         lib.wmco_l1_solve.argtypes = [P, P, P, I64, I64, D, D, D, I, P, P]
+        lib.wmco_fd_compute.argtypes = [P, I64, I64, D, P]
+        lib.wmco_fd_flow.argtypes = [P, I64, I64, D, D, I, P]
         _lib = lib
     return _lib
 
@@ -329,3 +333,20 @@ def l1_solve(f, lam: float = 1.0, alpha: float = 0.05, iters: int = 1, delta: fl
     _load().wmco_l1_solve(_p(f), _p(u0), _p(d0), H, W, float(lam), float(alpha), float(delta),
                           int(iters), _p(uo), _p(do))
     return uo, do
+
+
+def fd_compute(U, eps: float = 1e-12) -> np.ndarray:
+    """Central-difference H^w of eq. (rhs) with the guard eps (see O11)."""
+    U = _d(U)
+    H, W = U.shape
+    out = np.empty_like(U)
+    _load().wmco_fd_compute(_p(U), H, W, float(eps), _p(out))
+    return out
+
+
+def fd_flow(u0, delta: float = 0.1, iters: int = 1, eps: float = 1e-12) -> np.ndarray:
+    u0 = _d(u0)
+    H, W = u0.shape
+    out = np.empty_like(u0)
+    _load().wmco_fd_flow(_p(u0), H, W, float(delta), float(eps), int(iters), _p(out))
+    return out

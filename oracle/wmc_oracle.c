@@ -31,7 +31,9 @@
  *       selection m held fixed);
  *   O9  "listing mode": the Appendix A function's semantics (true 2-D
  *       convolution, zero padding, its candidate order), for cross-checks;
- *   O10 the l1-fidelity primal-dual iteration of Sec. 5.3 (A = I).
+ *   O10 the l1-fidelity primal-dual iteration of Sec. 5.3 (A = I);
+ *   O11 the conventional finite-difference WMC of eq. (rhs) and its flow
+ *       (the comparator of Sec. 5.4).
  *
  * Images are row-major H x W arrays of doubles, x = column, y = row
  * (downwards).  Functions never allocate more than O(H W) scratch.
@@ -368,4 +370,44 @@ void wmco_l1_solve(const double* f, const double* u0, const double* d0, int64_t 
     memcpy(Uout, ua, sizeof(double) * n);
     memcpy(dout, da, sizeof(double) * n);
     free(ua); free(ub); free(da); free(db);
+}
+
+/* O11: the conventional ("deriv") discretisation of the continuous WMC,
+ * eq. (rhs): H^w = Lap U - (U_y^2 U_yy + 2 U_x U_y U_xy + U_x^2 U_xx) /
+ * (U_x^2 + U_y^2), with second-order central differences at unit spacing and
+ * the replicate border.  The paper does not give its stencil or the guard at
+ * a vanishing gradient; here the denominator is U_x^2 + U_y^2 + eps, so that
+ * the normal term vanishes where the gradient does and H^w tends to the
+ * Laplacian there (cf. Sec. 3.3). */
+void wmco_fd_compute(const double* U, int64_t H, int64_t W, double eps, double* Hw) {
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) {
+            double c = U[y * W + x];
+            double e = ubar(U, H, W, y, x + 1), w = ubar(U, H, W, y, x - 1);
+            double s = ubar(U, H, W, y + 1, x), n = ubar(U, H, W, y - 1, x);
+            double se = ubar(U, H, W, y + 1, x + 1), ne = ubar(U, H, W, y - 1, x + 1);
+            double sw = ubar(U, H, W, y + 1, x - 1), nw = ubar(U, H, W, y - 1, x - 1);
+            double ux = 0.5 * (e - w), uy = 0.5 * (s - n);
+            double uxx = e - 2.0 * c + w, uyy = s - 2.0 * c + n;
+            double uxy = 0.25 * (se - ne - sw + nw);
+            double num = uy * uy * uyy + 2.0 * ux * uy * uxy + ux * ux * uxx;
+            Hw[y * W + x] = (uxx + uyy) - num / (ux * ux + uy * uy + eps);
+        }
+}
+
+/* iters curvature-flow steps U <- U + delta H^w_fd(U) from u0 (Sec. 3.5 with
+ * the conventional discretisation; the comparator of Sec. 5.4). */
+void wmco_fd_flow(const double* u0, int64_t H, int64_t W, double delta, double eps, int iters,
+                  double* Uout) {
+    int64_t n = H * W;
+    double* a = (double*)malloc(sizeof(double) * n);
+    double* h = (double*)malloc(sizeof(double) * n);
+    memcpy(a, u0, sizeof(double) * n);
+    for (int t = 0; t < iters; ++t) {
+        wmco_fd_compute(a, H, W, eps, h);
+        for (int64_t k = 0; k < n; ++k) a[k] += delta * h[k];
+    }
+    memcpy(Uout, a, sizeof(double) * n);
+    free(a);
+    free(h);
 }

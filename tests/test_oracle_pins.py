@@ -705,3 +705,52 @@ def test_l1_large_alpha_reduces_to_the_flow():
     uo, _ = oracle.l1_solve(f, lam=lam, alpha=alpha, iters=12, delta=delta)
     flow = oracle.solve(None, iters=12, delta=delta * lam, u0=f)
     assert np.allclose(uo, flow, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------------------
+# the conventional finite-difference WMC of eq. (rhs) (comparator of Sec. 5.4)
+# ---------------------------------------------------------------------------------------
+
+def test_fd_quadratic_closed_form():
+    """Central differences are exact on quadratics, so in the interior
+    H^w = 2a + 2c - (Uy^2 2c + 2 Ux Uy b + Ux^2 2a)/(Ux^2 + Uy^2)."""
+    rng = np.random.default_rng(40)
+    H, W = 9, 10
+    for _ in range(20):
+        a, b, c, d, e = (float(v) for v in rng.integers(-3, 4, size=5))
+        U = _quadratic(a, b, c, d, e, 0.5, H, W)
+        got = oracle.fd_compute(U, eps=0.0 + 1e-300)
+        for y in range(1, H - 1):
+            for x in range(1, W - 1):
+                ux, uy = 2 * a * x + b * y + d, b * x + 2 * c * y + e
+                g = ux * ux + uy * uy
+                if g == 0:
+                    want = 2 * a + 2 * c
+                else:
+                    want = 2 * a + 2 * c - (uy * uy * 2 * c + 2 * ux * uy * b + ux * ux * 2 * a) / g
+                assert got[y, x] == pytest.approx(want, rel=1e-12, abs=1e-12)
+
+
+def test_fd_paraboloid_and_plane():
+    """U = r^2: the normal diffusion term equals U_rr = 2, so H^w = 4 - 2 = 2
+    away from the centre, and the Laplacian 4 at the centre where the gradient
+    vanishes (the guard).  Planes give 0 in the interior."""
+    n, c = 13, 6
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    U = (x - c) ** 2 + (y - c) ** 2
+    got = oracle.fd_compute(U)
+    inner = got[1:-1, 1:-1].copy()
+    assert inner[c - 1, c - 1] == pytest.approx(4.0)
+    inner[c - 1, c - 1] = 2.0
+    assert np.allclose(inner, 2.0, atol=1e-12)
+    P = 0.3 * x - 0.7 * y
+    assert np.allclose(oracle.fd_compute(P)[1:-1, 1:-1], 0.0, atol=1e-14)
+
+
+def test_fd_flow_is_the_explicit_iteration():
+    rng = np.random.default_rng(41)
+    U = rng.uniform(0, 1, size=(12, 14))
+    a = U.copy()
+    for _ in range(5):
+        a = a + 0.1 * oracle.fd_compute(a)
+    assert np.allclose(oracle.fd_flow(U, 0.1, 5), a, atol=1e-14)
