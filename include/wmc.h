@@ -211,6 +211,21 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
                  const float* ckpt, int ckpt_every, const float* g_out, float* g_f, float* g_u0,
                  float* g_lam, void* ws, size_t ws_bytes, wmc_shape s, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * wmc_fd_compute -- the conventional discretisation of the continuous WMC of
+ * eq. (rhs), H^w = Lap U - (U_y^2 U_yy + 2 U_x U_y U_xy + U_x^2 U_xx) /
+ * (U_x^2 + U_y^2 + eps), with second-order central differences at unit
+ * spacing and the replicate border: the "deriv" comparator of Sec. 5.4.  The
+ * paper gives neither the stencil nor a guard; eps >= 0 makes the normal term
+ * vanish where the gradient does (H^w then tends to the Laplacian).
+ * wmc_fd_flow -- iters explicit curvature-flow steps U <- U + dt H^w_fd(U)
+ * from u0 (ws: wmc_solve_workspace(s) bytes when iters >= 2).
+ * Comparator kernels: one thread per pixel, not temporally blocked.
+ * ------------------------------------------------------------------------- */
+int wmc_fd_compute(const float* u, float* hw, float eps, wmc_shape s, void* stream);
+int wmc_fd_flow(const float* u0, float* u_out, int iters, float dt, float eps, void* ws,
+                size_t ws_bytes, wmc_shape s, void* stream);
+
 /* Checks on the current device that the wavefront lane shifts the kernels
  * rely on move data as expected; returns WMC_OK or WMC_EHIP/WMC_EUNSUPPORTED.
  * Synchronises the default stream. */

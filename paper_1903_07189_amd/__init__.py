@@ -6,9 +6,10 @@ gfx950 behind the C ABI of include/wmc.h (libwmc.so).  This package is the
 thin Python binding of that ABI; see :mod:`paper_1903_07189_amd.wmc`.
 """
 from .wmc import (WMCError, WMCSolve, SolveBatchedPlan, SolvePlan, autotune, backward, compute,
+                  fd_compute, fd_flow,
                   lib, release, selftest, shape_of, solve, solve_batched, solve_l1, solve_tuning,
                   step)
 
 __all__ = ["WMCError", "WMCSolve", "SolveBatchedPlan", "SolvePlan", "autotune", "backward",
-           "compute", "lib", "release", "selftest", "shape_of", "solve", "solve_batched",
+           "compute", "fd_compute", "fd_flow", "lib", "release", "selftest", "shape_of", "solve", "solve_batched",
            "solve_l1", "solve_tuning", "step"]

@@ -1347,6 +1347,58 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     return WMC_OK;
 }
 
+int wmc_fd_compute(const float* u, float* hw, float eps, wmc_shape s, void* stream) {
+    g_err.clear();
+    int rc = check_shape(s);
+    if (rc) return rc;
+    if (!u || !hw) return fail(WMC_EINVAL, "wmc_fd_compute: null pointer");
+    if (!(eps >= 0.0f) || !std::isfinite(eps)) return fail(WMC_EINVAL, "wmc_fd_compute: eps must be >= 0");
+    const int64_t ext = extent_elems(s);
+    if (overlaps(range_of(u, ext, 4), range_of(hw, ext, 4)))
+        return fail(WMC_EINVAL, "wmc_fd_compute: output overlaps input");
+    if (s.h > 65535 * 4 || s.n > 65535) return fail(WMC_EINVAL, "wmc_fd_compute: image too tall");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    const hipError_t e = launch_fd(u, hw, s.n, s.h, s.w, s.ld, s.ps, 0.0f, eps, false, as_stream(stream));
+    return e == hipSuccess ? WMC_OK : hip_fail(e, "wmc_fd_compute launch");
+}
+
+int wmc_fd_flow(const float* u0, float* u_out, int iters, float dt, float eps, void* ws,
+                size_t ws_bytes, wmc_shape s, void* stream) {
+    g_err.clear();
+    int rc = check_shape(s);
+    if (rc) return rc;
+    if (!u0 || !u_out) return fail(WMC_EINVAL, "wmc_fd_flow: null pointer");
+    if (iters < 0 || !std::isfinite(dt) || !(eps >= 0.0f) || !std::isfinite(eps))
+        return fail(WMC_EINVAL, "wmc_fd_flow: bad iters, dt or eps");
+    if (s.h > 65535 * 4 || s.n > 65535) return fail(WMC_EINVAL, "wmc_fd_flow: image too tall");
+    const int64_t ext = extent_elems(s);
+    if (iters >= 2 && (!ws || ws_bytes < wmc_solve_workspace(s)))
+        return fail(WMC_ENOMEM, "wmc_fd_flow: workspace smaller than wmc_solve_workspace()");
+    const Range ro = range_of(u_out, ext, 4), ri = range_of(u0, ext, 4);
+    const Range rw = range_of(iters >= 2 ? ws : nullptr, ext, 4);
+    if (overlaps(ro, ri) || overlaps(ro, rw) || overlaps(rw, ri))
+        return fail(WMC_EINVAL, "wmc_fd_flow: buffers overlap");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t st = as_stream(stream);
+    if (iters == 0) {
+        const hipError_t e = launch_copy_planes(u0, u_out, s.n, s.h, s.w, s.ld, s.ps, st);
+        return e == hipSuccess ? WMC_OK : hip_fail(e, "copy");
+    }
+    const float* src = u0;
+    for (int t = 0; t < iters; ++t) {
+        // the last step writes u_out, the ones before alternate with ws
+        float* dst = ((iters - 1 - t) % 2 == 0) ? u_out : static_cast<float*>(ws);
+        const hipError_t e = launch_fd(src, dst, s.n, s.h, s.w, s.ld, s.ps, dt, eps, true, st);
+        if (e != hipSuccess) return hip_fail(e, "wmc_fd_flow launch");
+        src = dst;
+    }
+    return WMC_OK;
+}
+
 int wmc_selftest(void) {
     g_err.clear();
     int dev;

@@ -98,4 +98,8 @@ hipError_t launch_adjoint_step(const AdjArgs& a, hipStream_t st);
 hipError_t launch_lambda_reduce(const float* lam_part, int64_t n, int nblk, float* g_lam,
                                 hipStream_t st);
 
+// Auxiliary kernels (wmc_aux.hip).
+hipError_t launch_fd(const float* u, float* out, int64_t n, int64_t h, int64_t w, int64_t ld,
+                     int64_t ps, float dt, float eps, bool flow, hipStream_t st);
+
 }  // namespace wmc

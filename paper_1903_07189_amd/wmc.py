@@ -48,7 +48,7 @@ class Tuning(ctypes.Structure):
 _lib = None
 EXPORTS = ["wmc_compute", "wmc_step", "wmc_solve_workspace", "wmc_set_stride",
            "wmc_num_checkpoints", "wmc_solve", "wmc_solve_tuning", "wmc_l1_workspace",
-           "wmc_solve_l1",
+           "wmc_solve_l1", "wmc_fd_compute", "wmc_fd_flow",
            "wmc_batched_workspace", "wmc_solve_batched", "wmc_autotune", "wmc_backward_workspace",
            "wmc_backward", "wmc_selftest", "wmc_last_error", "wmc_release"]
 
@@ -76,6 +76,8 @@ def lib():
     L.wmc_l1_workspace.argtypes = [Shape]
     L.wmc_l1_workspace.restype = SZ
     L.wmc_solve_l1.argtypes = [P, P, P, P, P, P, F, I, F, ctypes.POINTER(Tuning), P, SZ, Shape, P]
+    L.wmc_fd_compute.argtypes = [P, P, F, Shape, P]
+    L.wmc_fd_flow.argtypes = [P, P, I, F, F, P, SZ, Shape, P]
     L.wmc_batched_workspace.argtypes = [ctypes.POINTER(Image), I]
     L.wmc_batched_workspace.restype = SZ
     L.wmc_solve_batched.argtypes = [ctypes.POINTER(Image), I, P, I, F, ctypes.POINTER(Tuning), P,
@@ -90,6 +92,7 @@ def lib():
     L.wmc_release.argtypes = []
     L.wmc_release.restype = None
     for name in ("wmc_compute", "wmc_step", "wmc_solve", "wmc_solve_tuning", "wmc_solve_l1",
+                 "wmc_fd_compute", "wmc_fd_flow",
                  "wmc_solve_batched",
                  "wmc_autotune",
                  "wmc_backward", "wmc_selftest"):
@@ -238,6 +241,28 @@ def solve_l1(f: torch.Tensor, lam=1.0, alpha: float = 0.05, iters: int = 1, dt: 
     if squeeze:
         return out[0], dout[0]
     return out, dout
+
+
+def fd_compute(u: torch.Tensor, eps: float = 1e-12) -> torch.Tensor:
+    """Conventional central-difference H^w of eq. (rhs) (Sec. 5.4 comparator)."""
+    squeeze = u.dim() == 2
+    u = _planes(u).contiguous()
+    out = torch.empty_like(u)
+    check(lib().wmc_fd_compute(_ptr(u), _ptr(out), float(eps), shape_of(u), _stream()))
+    return out[0] if squeeze else out
+
+
+def fd_flow(u0: torch.Tensor, iters: int, dt: float = 0.1, eps: float = 1e-12) -> torch.Tensor:
+    """iters explicit curvature-flow steps with the conventional discretisation."""
+    squeeze = u0.dim() == 2
+    u0 = _planes(u0).contiguous()
+    s = shape_of(u0)
+    L = lib()
+    out = torch.empty_like(u0)
+    ws = torch.empty(max(1, L.wmc_solve_workspace(s) // 4), dtype=torch.float32, device=u0.device)
+    check(L.wmc_fd_flow(_ptr(u0), _ptr(out), int(iters), float(dt), float(eps), _ptr(ws),
+                        ws.numel() * 4, s, _stream()))
+    return out[0] if squeeze else out
 
 
 def solve_tuning(f: torch.Tensor | None, lam=1.0, dt: float = 0.0, u0: torch.Tensor | None = None):

@@ -160,3 +160,24 @@ def c5_batch(seed: int, batch: int = 32, side: int = 256):
 def random_unit(h: int, w: int, seed: int) -> np.ndarray:
     """i.i.d. U[0, 1) plane, float32 (unstructured parity input)."""
     return np.random.default_rng(seed).uniform(0.0, 1.0, size=(h, w)).astype(np.float32)
+
+
+def shapes(side: int = 128) -> np.ndarray:
+    """Piecewise-constant edge test image for the curvature-flow study, float32
+    (side, side): background 0.2, an axis-aligned cross (0.6) in the upper
+    left quadrant, a 45-degree diamond |x-cx| + |y-cy| <= r (0.8) in the upper
+    right, a disk (0.4) in the lower left and an axis-aligned square (0.9) in
+    the lower right.  No randomness."""
+    q = side // 4
+    ys = np.arange(side, dtype=np.float64)[:, None]
+    xs = np.arange(side, dtype=np.float64)[None, :]
+    img = np.full((side, side), 0.2)
+    r = 0.6 * q
+    arm = max(1, q // 4)
+    cross = ((np.abs(xs - q) <= arm) & (np.abs(ys - q) <= r)) | \
+            ((np.abs(ys - q) <= arm) & (np.abs(xs - q) <= r))
+    img[cross] = 0.6
+    img[np.abs(xs - 3 * q) + np.abs(ys - q) <= r] = 0.8
+    img[(xs - q) ** 2 + (ys - 3 * q) ** 2 <= r * r] = 0.4
+    img[(np.abs(xs - 3 * q) <= r) & (np.abs(ys - 3 * q) <= r)] = 0.9
+    return img.astype(np.float32)
