@@ -10,9 +10,10 @@ over memory (temporal blocking) and replays the launch sequence as a hipGraph.
 
 Printed: one JSON line with the metric (Gpixel-iterations/s), the roofline
 of the dominant kernel measured with HIP events on the stream the graph runs
-on, the FP64 CPU oracle timed on a bounded sample, and extras: the plain
-single-update kernel's HBM bandwidth and the uneven-size batched solve against
-per-image plain launches.
+on, the FP64 CPU oracle timed on bounded samples, and extras: the plain
+single-update kernel's HBM bandwidth (warm, cold and at 8192^2), the operator
+alone, the differentiable 16 x 512^2 solve's training step, and the
+uneven-size batched solve against per-image plain launches.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras]
 """
@@ -31,7 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Gpixel-iter/s of WMC step (fp32) and % HBM roofline; batched vs per-image"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz = 39.3
-# Arithmetic of one pixel update in the column-sum form:
+# Arithmetic of one pixel update in the column-sum form (wmc_device.hpp):
 # row quantities 3 + odd/even parts 11 + candidates 8 + selection 14 + update 3.
 ALGO_OPS_PER_PX_ITER = 39
 BYTES_PER_PX_PASS = 12         # read U and f, write U' once per pass over memory
@@ -93,10 +94,26 @@ def cpu_baseline(side: int, sample_iters: int):
     t0 = time.perf_counter()
     oracle.solve(f, lam=1.0, iters=sample_iters)
     dt = time.perf_counter() - t0
-    return {"value": round(side * side * sample_iters / dt / 1e9, 6), "unit": "Gpixel-iter/s",
-            "cores": 1, "kind": "oracle",
-            "sample": f"{side}x{side} input, {sample_iters} of the 200 iterations "
-                      f"({dt:.1f} s, FP64, one thread)"}
+    out = {"value": round(side * side * sample_iters / dt / 1e9, 6), "unit": "Gpixel-iter/s",
+           "cores": 1, "kind": "oracle",
+           "sample": f"{side}x{side} input, {sample_iters} of the 200 iterations "
+                     f"({dt:.1f} s, FP64, one thread)"}
+    # two more bounded samples: the 256 x 256 parity image in full (50
+    # iterations) and one 512 x 512 image of the differentiable workload,
+    # forward + adjoint of K = 20 steps
+    c1, _ = wmc_synth.c1()
+    t0 = time.perf_counter()
+    oracle.solve(c1[0], lam=1.0, iters=50)
+    t_c1 = time.perf_counter() - t0
+    c4, _ = wmc_synth.c4(batch=1)
+    g = np.random.default_rng(0).standard_normal((512, 512))
+    t0 = time.perf_counter()
+    oracle.solve_adjoint(g, f=c4[0, 0], lam=1.0, K=20)
+    t_c4 = time.perf_counter() - t0
+    out["samples"] = {"c1_256_50_iters_s": round(t_c1, 3),
+                      "c1_gpx_iter_s": round(256 * 256 * 50 / t_c1 / 1e9, 6),
+                      "c4_one_image_fwd_adjoint_s": round(t_c4, 3)}
+    return out
 
 
 def timed(fn, reps, stream, torch):
@@ -128,8 +145,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1",
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(sharding by image or by row band is a design only); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
@@ -245,6 +262,47 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side):
     ex["compute_4096"] = {"gpx_per_s": round(side * side / (ms * 1e-3) / 1e9, 1),
                           "gbs_incl_launch": round(8 * side * side / (ms * 1e-3) / 1e9, 1)}
     del h
+    # cold single update: four independent 4096^2 problems (768 MiB, three
+    # times the Infinity Cache) updated round-robin, so every launch finds its
+    # operands evicted; wmc_step launches enqueued back to back through the ABI
+    from paper_1903_07189_amd import wmc as M
+    L = M.lib()
+    us = [torch.rand_like(f) for _ in range(4)]
+    fs = [torch.rand_like(f) for _ in range(4)]
+    outs = [torch.empty_like(f) for _ in range(4)]
+    shp, st = M.shape_of(f), M._stream()
+
+    def run_cold():
+        for i in range(4):
+            M.check(L.wmc_step(M._ptr(us[i]), M._ptr(fs[i]), M._ptr(outs[i]), M._ptr(lam), 0.0,
+                               None, shp, st))
+    run_cold()
+    ms = timed(run_cold, 10, stream, torch) / 40
+    ex["step_T1_4096_cold"] = {"gbs": round(BYTES_PER_PX_PASS * side * side / (ms * 1e-3) / 1e9, 1),
+                               "us_per_launch": round(ms * 1e3, 2),
+                               "note": "wmc_step, 4 problems round-robin (768 MiB > Infinity Cache)"}
+    del us, fs, outs
+    # differentiable solve (16 x 512 x 512, K = 20, checkpoint every 5): one
+    # training step = fused forward with checkpoints + hand-written adjoint
+    noisy, clean = wmc_synth.c4()
+    x = torch.from_numpy(noisy[:, 0]).to(f.device)
+    y = torch.from_numpy(clean[:, 0]).to(f.device)
+    lam16 = torch.ones(16, device=f.device, requires_grad=True)
+    xg = x.clone().requires_grad_(True)
+
+    def train_step():
+        u = wmc.WMCSolve.apply(xg, lam16, 20)
+        loss = torch.mean((u - y) ** 2)
+        loss.backward()
+    train_step()
+    ms_t = timed(train_step, 5, stream, torch) / 5
+    ms_f = timed(lambda: wmc.solve(x, lam16.detach(), 20, ckpt_every=5), 5, stream, torch) / 5
+    pxs = 16 * 512 * 512 * 20
+    ex["c4_train_step"] = {"ms_forward_backward": round(ms_t, 3), "ms_forward_ckpt": round(ms_f, 3),
+                           "forward_gpx_iter_s": round(pxs / (ms_f * 1e-3) / 1e9, 1),
+                           "backward_gpx_step_s": round(pxs / ((ms_t - ms_f) * 1e-3) / 1e9, 1),
+                           "note": "backward = segment recompute + adjoint steps + lam reduction"}
+    del x, y, xg
     # uneven batch: 64 images x 3 channels, sides U{128..2048}, 100 iterations
     sizes = wmc_synth.c3_sizes()
     imgs = []

@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests cannot run without a device; skip them cleanly when there is none
-    # (the harness selects them with -m gpu on a GPU machine).
+    # (on a machine with an MI355X they are selected with -m gpu).
     try:
         import torch
         have_gpu = torch.cuda.is_available()
