@@ -116,6 +116,23 @@ def cpu_baseline(side: int, sample_iters: int):
     return out
 
 
+def train_step_fn(torch, wmc, wmc_synth, dev):
+    """One optimisation step's worth of work on the 16 x 512 x 512, K = 20
+    workload: the fused forward with checkpoints every 5 steps, the MSE loss
+    against the clean images, and backward through the adjoint to f and lam."""
+    noisy, clean = wmc_synth.c4()
+    x = torch.from_numpy(noisy[:, 0]).to(dev)
+    y = torch.from_numpy(clean[:, 0]).to(dev)
+    lam16 = torch.ones(16, device=dev, requires_grad=True)
+    xg = x.clone().requires_grad_(True)
+
+    def step():
+        u = wmc.WMCSolve.apply(xg, lam16, 20)
+        loss = torch.mean((u - y) ** 2)
+        loss.backward()
+    return step, x
+
+
 def timed(fn, reps, stream, torch):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -142,6 +159,9 @@ def main():
                     help="force the launch shape 'cols,tsteps,seg_rows' (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration for rocprofv3)")
+    ap.add_argument("--train-only", type=int, default=0, metavar="N",
+                    help="only run N training steps of the differentiable 16 x 512^2, K = 20 "
+                         "solve (profiling runs)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -169,6 +189,12 @@ def main():
         return
 
     wmc.selftest()
+    if args.train_only:
+        step, _ = train_step_fn(torch, wmc, wmc_synth, dev)
+        step()
+        ms = timed(step, args.train_only, stream, torch) / args.train_only
+        print(json.dumps({"workload": "16 x 512^2 K=20 training step", "ms": round(ms, 4)}))
+        return
     side, iters = args.side, args.iters
     noisy, _ = wmc_synth.c2(side=side)
     f = torch.from_numpy(noisy).to(dev)           # (1, side, side)
@@ -284,25 +310,17 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side):
     del us, fs, outs
     # differentiable solve (16 x 512 x 512, K = 20, checkpoint every 5): one
     # training step = fused forward with checkpoints + hand-written adjoint
-    noisy, clean = wmc_synth.c4()
-    x = torch.from_numpy(noisy[:, 0]).to(f.device)
-    y = torch.from_numpy(clean[:, 0]).to(f.device)
-    lam16 = torch.ones(16, device=f.device, requires_grad=True)
-    xg = x.clone().requires_grad_(True)
-
-    def train_step():
-        u = wmc.WMCSolve.apply(xg, lam16, 20)
-        loss = torch.mean((u - y) ** 2)
-        loss.backward()
+    train_step, x = train_step_fn(torch, wmc, wmc_synth, f.device)
     train_step()
     ms_t = timed(train_step, 5, stream, torch) / 5
-    ms_f = timed(lambda: wmc.solve(x, lam16.detach(), 20, ckpt_every=5), 5, stream, torch) / 5
+    lam16 = torch.ones(16, device=f.device)
+    ms_f = timed(lambda: wmc.solve(x, lam16, 20, ckpt_every=5), 5, stream, torch) / 5
     pxs = 16 * 512 * 512 * 20
     ex["c4_train_step"] = {"ms_forward_backward": round(ms_t, 3), "ms_forward_ckpt": round(ms_f, 3),
                            "forward_gpx_iter_s": round(pxs / (ms_f * 1e-3) / 1e9, 1),
                            "backward_gpx_step_s": round(pxs / ((ms_t - ms_f) * 1e-3) / 1e9, 1),
                            "note": "backward = segment recompute + adjoint steps + lam reduction"}
-    del x, y, xg
+    del x
     # uneven batch: 64 images x 3 channels, sides U{128..2048}, 100 iterations
     sizes = wmc_synth.c3_sizes()
     imgs = []

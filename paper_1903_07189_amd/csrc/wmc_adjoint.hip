@@ -1,20 +1,44 @@
 // wmc_adjoint.hip -- reverse-mode derivative of one WMC update for gfx950.
 //
-// With the selected half window m(x) held at its forward value the update
-//   U'(x) = U(x) + delta [(f(x) - U(x)) + lam/12 sum_o c_{m(x)}[o] U(clamp(x+o))]
-// (c_i = 12 h_i including the centre weight -12, Sec. 4.2) is affine in U, f
-// and its adjoint is a transposed, data-dependent stencil:
-//   g_prev(y) = keep g(y) + coef sum_{x, o: clamp(x+o) = y} c_{m(x)}[o] g(x)
-// keep = 1 - delta, coef = delta lam / 12 with a data term; keep = 1,
-// coef = delta / 12 for the flow.  Two kernels:
-//   k_adj_select : m(x) from U^t through the same per-pixel arithmetic as the
-//                  forward kernels (so it reproduces their selection bit for
-//                  bit), plus per-block partial sums of dL/dlam;
-//   k_adj_gather : the transposed stencil as a gather over the 3x3
-//                  neighbours, with the clamped taps of border pixels folded
-//                  in, plus dL/df += delta g.
-// dL/dlam per plane is reduced in a fixed order (no atomics) by
-// k_lam_reduce, so gradients are bitwise reproducible.
+// With the selected half window m(x) held at its forward value, the update
+//   U'(x) = U(x) + delta [(f(x) - U(x)) + lam/12 sum_o c_{m(x)}[o] Ub(x+o)]
+// (c_i = 12 h_i with the centre weight -12, Ub the replicate-padded U,
+// Sec. 4.2) is affine in U and f, and its adjoint is
+//   g_prev = keep g + coef Fold(acc),   acc(z) = sum_x c_{m(x)}[z - x] g(x)
+// over the padded grid z, with keep = 1 - delta, coef = delta lam / 12 (data
+// term) or keep = 1, coef = delta / 12 (flow); Fold adds the one-pixel ring of
+// the padded grid onto the border pixels it replicates.
+//
+// Every half-window kernel is c_i = a + sigma_i e_j(i): the even kernel
+// a = [1 2 1; 2 -12 2; 1 2 1] plus or minus one of four odd kernels e1, e2,
+// e5, e6 (the decomposition the forward evaluates, wmc_device.hpp).  With the
+// fields G = g and W_j = sigma g at pixels whose selection is in family j
+// (zero elsewhere), the data-dependent scatter becomes fixed stencils:
+//   acc = (a (x) G) - sum_j (e_j (x) W_j),
+// where (x) is the same correlation the forward computes (a is symmetric,
+// the e_j antisymmetric).  The adjoint therefore runs the forward's
+// column-sum form on five fields instead of gathering per-tap weights.
+//
+// k_adj_stream: one wave per work item -- a strip of 64*C columns with a halo
+// of halo_cols(C, 2) columns on both sides (so the first strip also holds the
+// virtual columns -2, -1 and the last one W, W+1) and a segment of R rows --
+// streaming down the rows.  At step n it
+//   - takes rows n of U, g and f (row and column indices clamped: the
+//     replicate border), prefetched three steps earlier;
+//   - stage A, row n-1: the selection from U rows n-2..n through the same
+//     per-pixel arithmetic as the forward (bitwise the same choice), the
+//     fields (zero outside the image), dL/df += delta g and the dL/dlam
+//     partial sum over the pixels the item owns;
+//   - stage B, row n-2: the five stencils from field rows n-3..n-1, the ring
+//     folds, and g_prev.
+// Fields vanish outside the image, so the stencils evaluated at the virtual
+// rows -1, H and columns -1, W are exactly the ring values to fold.
+//
+// dL/dlam: each work item writes one partial sum per step into its slot of
+// a buffer; k_lam_reduce adds, per plane and in a fixed order, the steps of a
+// checkpoint segment from the last to the first -- the same sequence of
+// additions whatever the segment length -- so gradients are bitwise
+// reproducible and independent of the checkpoint period.
 #include <hip/hip_runtime.h>
 
 #include "wmc_device.hpp"
@@ -22,171 +46,434 @@
 
 namespace wmc {
 
-// The eight half-window kernels of Sec. 4.2 times 12, [i][row][col], row 0
-// is the image row above the pixel, col 0 the column to its left.
-__constant__ int8_t kHalf12[8][3][3] = {
-    {{2, 2, 0}, {4, -12, 0}, {2, 2, 0}},  // h1 left
-    {{2, 4, 2}, {2, -12, 2}, {0, 0, 0}},  // h2 top
-    {{0, 2, 2}, {0, -12, 4}, {0, 2, 2}},  // h3 right
-    {{0, 0, 0}, {2, -12, 2}, {2, 4, 2}},  // h4 bottom
-    {{2, 4, 1}, {4, -12, 0}, {1, 0, 0}},  // h5 top-left
-    {{1, 4, 2}, {0, -12, 4}, {0, 0, 1}},  // h6 top-right
-    {{0, 0, 1}, {0, -12, 4}, {1, 4, 2}},  // h7 bottom-right
-    {{1, 0, 0}, {4, -12, 0}, {2, 4, 1}},  // h8 bottom-left
+constexpr int kAdjBlock = 256;  // 4 independent waves per workgroup
+constexpr int kAdjWaves = kAdjBlock / 64;
+
+// Row quantities of the five fields: G (s, centre), W1 (q), W2 (s), W5 (a, q),
+// W6 (a, q) -- what the stencils read.
+template <int C>
+struct FRow {
+    float gs[C], gc[C], q1[C], s2[C], a5[C], q5[C], a6[C], q6[C];
 };
 
-constexpr int kTX = 64, kTY = 4;  // pixels per block: 64 columns x 4 rows
-
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-// Row quantities of one image row at column x, with the replicate border,
-// computed exactly as make_row() does from the lane-neighbour values.
-__device__ __forceinline__ void row_at(const float* __restrict__ row, int x, int W, float& a,
-                                       float& s, float& q, float& c) {
-    const float l = row[x > 0 ? x - 1 : 0];
-    const float m = row[x];
-    const float r = row[x + 1 < W ? x + 1 : W - 1];
-    a = __builtin_fmaf(2.0f, m, l);
-    s = a + r;
-    q = l - r;
-    c = m;
+template <int C>
+__device__ __forceinline__ void zero_frow(FRow<C>& r) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        r.gs[e] = 0.0f; r.gc[e] = 0.0f; r.q1[e] = 0.0f; r.s2[e] = 0.0f;
+        r.a5[e] = 0.0f; r.q5[e] = 0.0f; r.a6[e] = 0.0f; r.q6[e] = 0.0f;
+    }
 }
 
-__global__ __launch_bounds__(kTX* kTY) void k_adj_select(AdjArgs A) {
-    const int x = blockIdx.x * kTX + threadIdx.x;
-    const int y = blockIdx.y * kTY + threadIdx.y;
-    const int p = blockIdx.z;
-    const int H = (int)A.h, W = (int)A.w;
-    const bool data = A.f != nullptr;
+// Left / right neighbours of a field row; zero beyond the wave's edge lanes
+// (halo columns, whose results are not used).
+template <int C>
+__device__ __forceinline__ void nbrs(const float (&x)[C], float (&l)[C], float (&r)[C]) {
+    const float lft = from_lower_lane(0.0f, x[C - 1]);
+    const float rgt = from_upper_lane(0.0f, x[0]);
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        l[e] = (e == 0) ? lft : x[e - 1];
+        r[e] = (e == C - 1) ? rgt : x[e + 1];
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void make_frow(const float (&G)[C], const float (&W1)[C],
+                                          const float (&W2)[C], const float (&W5)[C],
+                                          const float (&W6)[C], FRow<C>& o) {
+    float l[C], r[C];
+    nbrs(G, l, r);
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        o.gs[e] = __builtin_fmaf(2.0f, G[e], l[e]) + r[e];
+        o.gc[e] = G[e];
+    }
+    nbrs(W1, l, r);
+#pragma unroll
+    for (int e = 0; e < C; ++e) o.q1[e] = l[e] - r[e];
+    nbrs(W2, l, r);
+#pragma unroll
+    for (int e = 0; e < C; ++e) o.s2[e] = __builtin_fmaf(2.0f, W2[e], l[e]) + r[e];
+    nbrs(W5, l, r);
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        o.a5[e] = __builtin_fmaf(2.0f, W5[e], l[e]);
+        o.q5[e] = l[e] - r[e];
+    }
+    nbrs(W6, l, r);
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        o.a6[e] = __builtin_fmaf(2.0f, W6[e], l[e]);
+        o.q6[e] = l[e] - r[e];
+    }
+}
+
+// acc at the middle row: (a (x) G) - sum_j (e_j (x) W_j), each stencil in the
+// column-sum form of the forward's parts().
+template <int C>
+__device__ __forceinline__ float stencil(const FRow<C>& t, const FRow<C>& m, const FRow<C>& b,
+                                         int e) {
+    const float A = __builtin_fmaf(-16.0f, m.gc[e], __builtin_fmaf(2.0f, m.gs[e], t.gs[e] + b.gs[e]));
+    const float E1 = __builtin_fmaf(2.0f, m.q1[e], t.q1[e] + b.q1[e]);
+    const float E2 = t.s2[e] - b.s2[e];
+    const float E5 = __builtin_fmaf(2.0f, m.q5[e], (t.a5[e] - b.a5[e]) + b.q5[e]);
+    const float E6 = __builtin_fmaf(-2.0f, m.q6[e], (t.a6[e] - b.a6[e]) - t.q6[e]);
+    return A - ((E1 + E2) + (E5 + E6));
+}
+
+struct AdjItem {
+    const float* u;
+    const float* f;
+    const float* g;
+    float* g_prev;
+    float* g_f;
+    int64_t ld;
+    int H, W;
+    int x0, ox0, ox1;  // first loaded column, owned columns [ox0, ox1)
+    int y0, y1;        // owned rows
+    float delta, lam, keep, coef;
+    bool dlam_default;  // delta = 1/(1+lam): dU'/dlam has the delta'(lam) term
+};
+
+template <int P>
+struct APhase {
+    static constexpr int value = P;
+};
+
+// Runs one work item; returns the item's dL/dlam partial sum (valid in lane 0
+// after the wave reduction, data mode only).  EDGE: first or last strip
+// (clamped scalar loads, column folds).  VEC: rows are 4C-byte aligned and the
+// strip lies inside the image, so every lane moves its C columns with one
+// vector access.
+template <int C, bool DATA, bool EDGE, bool VEC>
+__device__ __forceinline__ float run_adj(const AdjItem it) {
+    const int lane = threadIdx.x & 63;
+    const int xb = it.x0 + C * lane;
+    const int H = it.H, W = it.W;
+
+    bool inimg[C], own[C], isL[C], isR[C];
+    int xc[C];
+    bool all_own = true;
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        const int x = xb + e;
+        inimg[e] = x >= 0 && x < W;
+        own[e] = x >= it.ox0 && x < it.ox1;
+        all_own = all_own && own[e];
+        isL[e] = x == 0;
+        isR[e] = x == W - 1;
+        xc[e] = x < 0 ? 0 : (x < W ? x : W - 1);
+    }
+    const bool never[C] = {};
+
+    float pu[3][C], pg[3][C], pfv[3][C], pgf[3][C];  // prefetch slots
+    RowQ<C> uw[3];                                    // U row quantities, rows n-2..n
+    FRow<C> fw[3];                                    // field rows n-3..n-1
+    float gr[3][C], fr[3][C], gfr[3][C];              // g, f and dL/df rows n-2..n
+    float topfold[C], pend[C], pendg[C];  // row -1 fold; row H-1 held until row H is done
+#pragma unroll
+    for (int j = 0; j < 3; ++j) zero_frow(fw[j]);
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        topfold[e] = 0.0f;
+        pend[e] = 0.0f;
+        pendg[e] = 0.0f;
+    }
     float contrib = 0.0f;
-    if (x < W && y < H) {
-        const float* u = A.u + (int64_t)p * A.ps;
-        const int64_t k = (int64_t)y * A.ld + x;
-        float ta, ts, tq, tc, ma, ms, mq, mc, ba, bs, bq, bc;
-        row_at(u + (int64_t)clampi(y - 1, 0, H - 1) * A.ld, x, W, ta, ts, tq, tc);
-        row_at(u + (int64_t)y * A.ld, x, W, ma, ms, mq, mc);
-        row_at(u + (int64_t)clampi(y + 1, 0, H - 1) * A.ld, x, W, ba, bs, bq, bc);
-        int idx;
-        const float S = select_x12_idx(parts(ta, ts, tq, ms, mq, mc, ba, bs, bq), idx);
-        A.sel[(int64_t)p * A.ps + k] = (uint8_t)idx;
-        if (data) {
-            const float lam = A.lam ? A.lam[p] : 0.0f;
-            const Coef cf = make_coef(lam, A.dt, true);
-            const float hd = to_hd(S);
-            const float g = A.g[(int64_t)p * A.ps + k];
-            float dudl = cf.delta * hd;
-            if (!(A.dt > 0.0f)) {
-                const float fv = A.f[(int64_t)p * A.ps + k];
-                dudl -= cf.delta * cf.delta * ((fv - mc) + lam * hd);
-            }
-            contrib = g * dudl;
+
+    const int n0 = it.y0 - 2, nend = it.y1 + 2;
+
+    auto load = [&](float (&u)[C], float (&g)[C], float (&fv)[C], float (&gf)[C], int row) {
+        const int rr = row < 0 ? 0 : (row < H ? row : H - 1);
+        const float* up = it.u + (int64_t)rr * it.ld;
+        const float* gp = it.g + (int64_t)rr * it.ld;
+        const float* fp = DATA ? it.f + (int64_t)rr * it.ld : nullptr;
+        // dL/df is read-modify-written on owned rows only (wave-uniform test)
+        if (DATA && it.g_f && row >= it.y0 && row < it.y1) {
+            const float* qp = it.g_f + (int64_t)rr * it.ld;
+#pragma unroll
+            for (int e = 0; e < C; ++e) gf[e] = own[e] ? ld_at<float>(qp, (uint32_t)(xb + e)) : 0.0f;
         }
+        if constexpr (VEC && C == 4) {
+            const float4 a = ld_at<float4>(up, (uint32_t)xb);
+            const float4 b = ld_at<float4>(gp, (uint32_t)xb);
+            u[0] = a.x; u[1] = a.y; u[2] = a.z; u[3] = a.w;
+            g[0] = b.x; g[1] = b.y; g[2] = b.z; g[3] = b.w;
+            if constexpr (DATA) {
+                const float4 c = ld_at<float4>(fp, (uint32_t)xb);
+                fv[0] = c.x; fv[1] = c.y; fv[2] = c.z; fv[3] = c.w;
+            }
+        } else if constexpr (VEC && C == 2) {
+            const float2 a = ld_at<float2>(up, (uint32_t)xb);
+            const float2 b = ld_at<float2>(gp, (uint32_t)xb);
+            u[0] = a.x; u[1] = a.y;
+            g[0] = b.x; g[1] = b.y;
+            if constexpr (DATA) {
+                const float2 c = ld_at<float2>(fp, (uint32_t)xb);
+                fv[0] = c.x; fv[1] = c.y;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < C; ++e) {
+                u[e] = ld_at<float>(up, (uint32_t)xc[e]);
+                g[e] = ld_at<float>(gp, (uint32_t)xc[e]);
+                if constexpr (DATA) fv[e] = ld_at<float>(fp, (uint32_t)xc[e]);
+            }
+        }
+    };
+
+    auto store = [&](int r, const float (&acc)[C], const float (&gv)[C]) {
+        float* dp = it.g_prev + (int64_t)r * it.ld;
+        float v[C];
+#pragma unroll
+        for (int e = 0; e < C; ++e) v[e] = __builtin_fmaf(it.coef, acc[e], it.keep * gv[e]);
+        if constexpr (VEC) {
+            if (all_own) {
+                if constexpr (C == 4) st_at<float4>(dp, (uint32_t)xb, make_float4(v[0], v[1], v[2], v[3]));
+                else if constexpr (C == 2) st_at<float2>(dp, (uint32_t)xb, make_float2(v[0], v[1]));
+                else st_at<float>(dp, (uint32_t)xb, v[0]);
+                return;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < C; ++e)
+            if (own[e]) st_at<float>(dp, (uint32_t)(xb + e), v[e]);
+    };
+
+    int n = n0;
+
+    auto step = [&](auto phase_tag) {
+        constexpr int P = decltype(phase_tag)::value;
+        constexpr int PM = (P + 2) % 3;  // row n-1
+        constexpr int PT = (P + 1) % 3;  // row n-2 (and n+1 for the prefetch)
+        // row n out of its prefetch slot, then refill the slot with row n+3
+        float m[C];
+#pragma unroll
+        for (int e = 0; e < C; ++e) {
+            m[e] = pu[P][e];
+            gr[P][e] = pg[P][e];
+            fr[P][e] = DATA ? pfv[P][e] : 0.0f;
+            gfr[P][e] = DATA ? pgf[P][e] : 0.0f;
+        }
+        if (n + 3 <= nend) load(pu[P], pg[P], pfv[P], pgf[P], n + 3);
+        make_row<C, false>(m, never, uw[P]);
+
+        // stage A: fields of row rho = n-1 (zero outside the image)
+        const int rho = n - 1;
+        if (rho >= it.y0 - 1) {
+            float G[C], W1[C], W2[C], W5[C], W6[C];
+            if (rho >= 0 && rho < H) {
+                const bool owned_row = rho >= it.y0 && rho < it.y1;
+                float* gfp = (DATA && it.g_f && owned_row) ? it.g_f + (int64_t)rho * it.ld : nullptr;
+#pragma unroll
+                for (int e = 0; e < C; ++e) {
+                    const Odd o = parts(uw[PT].a[e], uw[PT].s[e], uw[PT].q[e], uw[PM].s[e],
+                                        uw[PM].q[e], uw[PM].c[e], uw[P].a[e], uw[P].s[e],
+                                        uw[P].q[e]);
+                    int idx;
+                    const float S = select_x12_idx(o, idx);
+                    const float gv = inimg[e] ? gr[PM][e] : 0.0f;
+                    const float sg = (idx & 2) ? -gv : gv;
+                    const int fam = idx & 5;
+                    G[e] = gv;
+                    W1[e] = fam == 0 ? sg : 0.0f;
+                    W2[e] = fam == 1 ? sg : 0.0f;
+                    W5[e] = fam == 4 ? sg : 0.0f;
+                    W6[e] = fam == 5 ? sg : 0.0f;
+                    if constexpr (DATA) {
+                        if (owned_row && own[e]) {
+                            const float hd = to_hd(S);
+                            float dudl = it.delta * hd;
+                            if (it.dlam_default)
+                                dudl -= it.delta * it.delta * ((fr[PM][e] - uw[PM].c[e]) + it.lam * hd);
+                            contrib = __builtin_fmaf(gv, dudl, contrib);
+                            if (gfp) st_at<float>(gfp, (uint32_t)(xb + e),
+                                                  __builtin_fmaf(it.delta, gv, gfr[PM][e]));
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < C; ++e) {
+                    G[e] = 0.0f; W1[e] = 0.0f; W2[e] = 0.0f; W5[e] = 0.0f; W6[e] = 0.0f;
+                }
+            }
+            make_frow(G, W1, W2, W5, W6, fw[PM]);
+        }
+
+        // stage B: row r = n-2
+        const int r = n - 2;
+        const bool owned = r >= it.y0 && r < it.y1;
+        const bool top = r == -1 && it.y0 == 0;
+        const bool bot = r == H && it.y1 == H;
+        if (owned || top || bot) {
+            float acc[C];
+#pragma unroll
+            for (int e = 0; e < C; ++e) acc[e] = stencil(fw[P], fw[PT], fw[PM], e);
+            if constexpr (EDGE) {
+                // column ring: virtual column -1 onto column 0, W onto W-1
+                const float lft = from_lower_lane(0.0f, acc[C - 1]);
+                const float rgt = from_upper_lane(0.0f, acc[0]);
+                float add[C];
+#pragma unroll
+                for (int e = 0; e < C; ++e) {
+                    const float fromL = (e == 0) ? lft : acc[e - 1];
+                    const float fromR = (e == C - 1) ? rgt : acc[e + 1];
+                    add[e] = isL[e] ? (isR[e] ? fromL + fromR : fromL) : (isR[e] ? fromR : 0.0f);
+                }
+#pragma unroll
+                for (int e = 0; e < C; ++e)
+                    if (isL[e] || isR[e]) acc[e] += add[e];
+            }
+            if (top) {
+#pragma unroll
+                for (int e = 0; e < C; ++e) topfold[e] = acc[e];
+            } else if (bot) {
+#pragma unroll
+                for (int e = 0; e < C; ++e) acc[e] += pend[e];
+                store(H - 1, acc, pendg);
+            } else {
+                if (r == 0) {
+#pragma unroll
+                    for (int e = 0; e < C; ++e) acc[e] += topfold[e];
+                }
+                if (r == H - 1) {
+#pragma unroll
+                    for (int e = 0; e < C; ++e) {
+                        pend[e] = acc[e];
+                        pendg[e] = gr[PT][e];
+                    }
+                } else {
+                    store(r, acc, gr[PT]);
+                }
+            }
+        }
+    };
+
+#pragma unroll
+    for (int j = 0; j < 3; ++j) load(pu[j], pg[j], pfv[j], pgf[j], n0 + j);
+
+    while (true) {
+        step(APhase<0>{});
+        if (++n > nend) break;
+        step(APhase<1>{});
+        if (++n > nend) break;
+        step(APhase<2>{});
+        if (++n > nend) break;
     }
-    if (!data) return;
-    // fixed-order block reduction of dL/dlam
-    __shared__ float red[kTX * kTY];
-    const int t = threadIdx.y * kTX + threadIdx.x;
-    red[t] = contrib;
-    __syncthreads();
-    for (int w = kTX * kTY / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
-    if (t == 0) {
-        const int nblk = gridDim.x * gridDim.y;
-        A.lam_part[(int64_t)p * nblk + blockIdx.y * gridDim.x + blockIdx.x] = red[0];
-    }
+
+    // fixed-order butterfly over the wave
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
+    return contrib;
 }
 
-__global__ __launch_bounds__(kTX* kTY) void k_adj_gather(AdjArgs A) {
-    const int x = blockIdx.x * kTX + threadIdx.x;
-    const int y = blockIdx.y * kTY + threadIdx.y;
-    const int p = blockIdx.z;
+template <int C, bool DATA>
+__global__ __launch_bounds__(kAdjBlock) void k_adj_stream(AdjArgs A) {
+    // wave index, made visibly wave-uniform so the item bookkeeping is scalar
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t per_plane = (int64_t)A.nseg * A.nstrip;
+    const int64_t total = A.n * per_plane;
+    const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * kAdjWaves + wv;
+    if (item >= total) return;
+    const int p = (int)(item / per_plane);
+    const int rem = (int)(item - (int64_t)p * per_plane);
+    const int seg = rem / A.nstrip;
+    const int strip = rem - seg * A.nstrip;
     const int H = (int)A.h, W = (int)A.w;
-    if (x >= W || y >= H) return;
-    const bool data = A.f != nullptr;
-    const float lam = (data && A.lam) ? A.lam[p] : 0.0f;
-    const Coef cf = make_coef(lam, A.dt, data);
-    const float keep = data ? 1.0f - cf.delta : 1.0f;
-    const float coef = data ? cf.delta * cf.lam12 : cf.delta12;
-    const int64_t base = (int64_t)p * A.ps;
-    const float* g = A.g + base;
-    const uint8_t* sel = A.sel + base;
 
-    // For each neighbour offset d along one axis, the bit set of kernel taps o
-    // (bit o+1) of the neighbour x = y + d that land on y after clamping.
-    unsigned mr[3], mc[3];
-#pragma unroll
-    for (int d = -1; d <= 1; ++d) {
-        unsigned br = 0, bc = 0;
-        const int xr = y + d, xc = x + d;
-#pragma unroll
-        for (int o = -1; o <= 1; ++o) {
-            if (xr >= 0 && xr < H && clampi(xr + o, 0, H - 1) == y) br |= 1u << (o + 1);
-            if (xc >= 0 && xc < W && clampi(xc + o, 0, W - 1) == x) bc |= 1u << (o + 1);
-        }
-        mr[d + 1] = br;
-        mc[d + 1] = bc;
-    }
-    float acc = 0.0f;
-#pragma unroll
-    for (int dr = 0; dr < 3; ++dr) {
-        if (!mr[dr]) continue;
-#pragma unroll
-        for (int dc = 0; dc < 3; ++dc) {
-            if (!mc[dc]) continue;
-            const int64_t kx = (int64_t)(y + dr - 1) * A.ld + (x + dc - 1);
-            const int m = sel[kx];
-            int w = 0;
-#pragma unroll
-            for (int orr = 0; orr < 3; ++orr) {
-                if (!((mr[dr] >> orr) & 1u)) continue;
-#pragma unroll
-                for (int oc = 0; oc < 3; ++oc)
-                    if ((mc[dc] >> oc) & 1u) w += kHalf12[m][orr][oc];
-            }
-            acc = __builtin_fmaf((float)w, g[kx], acc);
-        }
-    }
-    const int64_t k = (int64_t)y * A.ld + x;
-    const float gy = g[k];
-    A.g_prev[base + k] = __builtin_fmaf(coef, acc, keep * gy);
-    if (data && A.g_f) A.g_f[base + k] += cf.delta * gy;
+    AdjItem it;
+    const int64_t off = (int64_t)p * A.ps;
+    it.u = A.u + off;
+    it.f = DATA ? A.f + off : nullptr;
+    it.g = A.g + off;
+    it.g_prev = A.g_prev + off;
+    it.g_f = (DATA && A.g_f) ? A.g_f + off : nullptr;
+    it.ld = A.ld;
+    it.H = H;
+    it.W = W;
+    const int hb = halo_cols(C, 2), step = 64 * C - 2 * hb;
+    it.x0 = strip * step - hb;
+    it.ox0 = strip * step;
+    it.ox1 = it.ox0 + step < W ? it.ox0 + step : W;
+    it.y0 = seg * A.R;
+    it.y1 = it.y0 + A.R < H ? it.y0 + A.R : H;
+    const float lam = (DATA && A.lam) ? A.lam[p] : 0.0f;
+    const Coef cf = make_coef(lam, A.dt, DATA);
+    it.delta = cf.delta;
+    it.lam = lam;
+    it.keep = DATA ? 1.0f - cf.delta : 1.0f;
+    it.coef = DATA ? cf.delta * cf.lam12 : cf.delta12;
+    it.dlam_default = !(A.dt > 0.0f);
+    const bool edge = it.x0 < 0 || it.x0 + 64 * C > W;
+    float c;
+    if (edge) c = run_adj<C, DATA, true, false>(it);
+    else if (A.vec) c = run_adj<C, DATA, false, true>(it);
+    else c = run_adj<C, DATA, false, false>(it);
+    if (DATA && A.part && (threadIdx.x & 63) == 0) A.part[(int64_t)A.slot * total + item] = c;
 }
 
-__global__ __launch_bounds__(256) void k_lam_reduce(const float* __restrict__ part, int nblk,
+// g_lam[p] += the step partial sums of plane p, steps from the last slot to
+// the first, each a fixed-order sum over the plane's work items.
+__global__ __launch_bounds__(256) void k_lam_reduce(const float* __restrict__ part, int steps,
+                                                    int64_t total, int64_t per_plane,
                                                     float* __restrict__ g_lam) {
     const int p = blockIdx.x;
     __shared__ float red[256];
-    float s = 0.0f;
-    for (int i = threadIdx.x; i < nblk; i += 256) s += part[(int64_t)p * nblk + i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    for (int t = steps - 1; t >= 0; --t) {
+        const float* q = part + (int64_t)t * total + (int64_t)p * per_plane;
+        float s = 0.0f;
+        for (int64_t i = threadIdx.x; i < per_plane; i += 256) s += q[i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) g_lam[p] += red[0];
         __syncthreads();
     }
-    if (threadIdx.x == 0) g_lam[p] += red[0];
 }
 
-int adj_blocks_per_plane(int64_t h, int64_t w) {
-    return (int)(((w + kTX - 1) / kTX) * ((h + kTY - 1) / kTY));
+int adj_strip_count(int W, int C) {
+    const int step = 64 * C - 2 * halo_cols(C, 2);
+    return (W + step - 1) / step;
 }
+
+int adj_rows(int64_t n, int64_t h, int64_t w, int C) {
+    // about 8K work items (several rounds of waves on 256 CUs), 16..128 rows
+    const int64_t rows_total = n * h * adj_strip_count((int)w, C);
+    int R = 16;
+    while (R < 128 && rows_total / R > 8192) R *= 2;
+    return R;
+}
+
+int64_t adj_items(int64_t n, int64_t h, int64_t w, int C) {
+    return n * seg_count((int)h, adj_rows(n, h, w, C)) * adj_strip_count((int)w, C);
+}
+
+using AdjFn = void (*)(AdjArgs);
 
 hipError_t launch_adjoint_step(const AdjArgs& a, hipStream_t st) {
-    const dim3 grid((unsigned)((a.w + kTX - 1) / kTX), (unsigned)((a.h + kTY - 1) / kTY),
-                    (unsigned)a.n);
-    const dim3 block(kTX, kTY);
-    hipLaunchKernelGGL(k_adj_select, grid, block, 0, st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_gather, grid, block, 0, st, a);
+    const bool data = a.f != nullptr;
+    AdjFn fn = nullptr;
+    switch (a.C) {
+        case 1: fn = data ? k_adj_stream<1, true> : k_adj_stream<1, false>; break;
+        case 2: fn = data ? k_adj_stream<2, true> : k_adj_stream<2, false>; break;
+        case 4: fn = data ? k_adj_stream<4, true> : k_adj_stream<4, false>; break;
+        default: return hipErrorInvalidValue;
+    }
+    const int64_t total = a.n * (int64_t)a.nseg * a.nstrip;
+    const int64_t blocks = (total + kAdjWaves - 1) / kAdjWaves;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kAdjBlock), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_lambda_reduce(const float* lam_part, int64_t n, int nblk, float* g_lam,
-                                hipStream_t st) {
-    hipLaunchKernelGGL(k_lam_reduce, dim3((unsigned)n), dim3(256), 0, st, lam_part, nblk, g_lam);
+hipError_t launch_lambda_reduce(const float* part, int steps, int64_t total, int64_t per_plane,
+                                int64_t n, float* g_lam, hipStream_t st) {
+    hipLaunchKernelGGL(k_lam_reduce, dim3((unsigned)n), dim3(256), 0, st, part, steps, total,
+                       per_plane, g_lam);
     return hipGetLastError();
 }
 

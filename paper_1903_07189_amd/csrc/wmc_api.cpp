@@ -1240,9 +1240,12 @@ size_t wmc_backward_workspace(wmc_shape s, int iters, int ckpt_every) {
     const int c = std::min(ckpt_every, std::max(iters, 1));
     const size_t states = (size_t)std::max(c - 1, 0) * set;
     const size_t grads = 2 * set;
-    const size_t sel = (size_t)(set_stride_elems(s) + 255) / 256 * 256;
-    const size_t part = (size_t)s.n * adj_blocks_per_plane(s.h, s.w) * sizeof(float);
-    return states + grads + sel + (part + 255) / 256 * 256;
+    // dL/dlam partial sums: one per work item and step of a segment, sized for
+    // the column width with the most work items
+    int64_t items = 0;
+    for (int C : {1, 2, 4}) items = std::max(items, adj_items(s.n, s.h, s.w, C));
+    const size_t part = (size_t)c * (size_t)items * sizeof(float);
+    return states + grads + (part + 255) / 256 * 256;
 }
 
 int wmc_backward(const float* f, const float* u0, const float* lam, int iters, float dt,
@@ -1277,14 +1280,33 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     w += set * sizeof(float);
     float* gB = reinterpret_cast<float*>(w);
     w += set * sizeof(float);
-    uint8_t* sel = reinterpret_cast<uint8_t*>(w);
-    w += (size_t)(set + 255) / 256 * 256;
     float* part = reinterpret_cast<float*>(w);
-    const int nblk = adj_blocks_per_plane(s.h, s.w);
     const bool data = f != nullptr;
-    const int mode = data ? kModeData : kModeFlow;
-    const int C1 = 1;
+    // recompute launches: plain single sweeps, paired columns when aligned
+    const int C1 = std::min(2, vec_cols({ckpt, states, f, u0}, s.ld, s.n > 1 ? s.ps : 0));
     const int R1 = default_rows(s.n, s.h, s.w, C1, 1, num_cu(dev));
+    // adjoint launches (WMC_ADJ_COLS=2|4 selects wider lanes)
+    const char* env_cols = std::getenv("WMC_ADJ_COLS");
+    int CA = 1;
+    if (env_cols && (std::atoi(env_cols) == 2 || std::atoi(env_cols) == 4)) CA = std::atoi(env_cols);
+    const bool vecA = vec_cols({ckpt, states, f, gA, gB, g_f}, s.ld, s.n > 1 ? s.ps : 0) >= CA;
+    AdjArgs a{};
+    a.f = f;
+    a.g_f = data ? g_f : nullptr;
+    a.part = (data && g_lam) ? part : nullptr;
+    a.lam = lam;
+    a.dt = dt;
+    a.n = s.n;
+    a.h = s.h;
+    a.w = s.w;
+    a.ld = s.ld;
+    a.ps = s.ps;
+    a.C = CA;
+    a.R = adj_rows(s.n, s.h, s.w, CA);
+    a.nstrip = adj_strip_count((int)s.w, CA);
+    a.nseg = seg_count((int)s.h, a.R);
+    a.vec = vecA ? 1 : 0;
+    const int64_t items = (int64_t)s.n * a.nstrip * a.nseg;
     hipError_t e;
     if (g_lam) {
         e = launch_fill_f32(g_lam, s.n, 0.0f, st);
@@ -1311,31 +1333,19 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
             st_ptr[t - t0] = dst;
         }
         for (int t = t1 - 1; t >= t0; --t) {
-            AdjArgs a{};
             a.u = st_ptr[t - t0];
-            a.f = f;
             a.g = gcur;
             a.g_prev = gnext;
-            a.g_f = data ? g_f : nullptr;
-            a.sel = sel;
-            a.lam_part = part;
-            a.lam = lam;
-            a.dt = dt;
-            a.n = s.n;
-            a.h = s.h;
-            a.w = s.w;
-            a.ld = s.ld;
-            a.ps = s.ps;
+            a.slot = t - t0;
             e = launch_adjoint_step(a, st);
             if (e != hipSuccess) return hip_fail(e, "adjoint launch");
-            if (data && g_lam) {
-                e = launch_lambda_reduce(part, s.n, nblk, g_lam, st);
-                if (e != hipSuccess) return hip_fail(e, "lambda reduction");
-            }
             std::swap(gcur, gnext);
         }
+        if (a.part) {
+            e = launch_lambda_reduce(part, t1 - t0, items, items / s.n, s.n, g_lam, st);
+            if (e != hipSuccess) return hip_fail(e, "lambda reduction");
+        }
     }
-    (void)mode;
     if (g_u0) {
         e = launch_copy_planes(gcur, g_u0, s.n, s.h, s.w, s.ld, s.ps, st);
         if (e != hipSuccess) return hip_fail(e, "copy");

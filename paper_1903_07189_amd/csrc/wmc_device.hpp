@@ -33,6 +33,26 @@ namespace wmc {
 
 constexpr int kWave = 64;
 
+// Maps blockIdx.x so that the blocks the hardware places on one XCD (it deals
+// blocks round-robin over the 8 XCDs) process one contiguous range of work
+// items: neighbouring strips then share halo rows in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
+    const int64_t q = G / 8, r = G % 8, x = b % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
+// Global memory access with a wave-uniform row pointer and a 32-bit per-lane
+// byte offset, so that the loads and stores use the scalar-base addressing
+// form (no 64-bit address arithmetic per lane).
+template <class V>
+__device__ __forceinline__ V ld_at(const float* row, uint32_t col) {
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(row) + col * 4u);
+}
+template <class V>
+__device__ __forceinline__ void st_at(float* row, uint32_t col, V v) {
+    *reinterpret_cast<V*>(reinterpret_cast<char*>(row) + col * 4u) = v;
+}
+
 // Lane L receives `src` of lane L-1; lane 0 keeps `old` (DPP wave_shr:1 with
 // bound_ctrl off).  Passing a lane's own value as `old` makes lane 0 see its
 // own value, i.e. the replicate border when lane 0 holds image column 0.

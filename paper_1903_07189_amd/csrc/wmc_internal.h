@@ -87,16 +87,22 @@ struct AdjArgs {
     const float* g;     // dL/dU^{t+1}
     float* g_prev;      // dL/dU^t (out)
     float* g_f;         // dL/df accumulator (data mode) or null
-    uint8_t* sel;       // selection map scratch (1 byte per element, layout of u)
-    float* lam_part;    // per plane: partial sums of dL/dlam, nblk_per_plane each
+    float* part;        // dL/dlam partial sums, [slot][item] (data mode) or null
     const float* lam;
     float dt;
     int64_t n, h, w, ld, ps;
+    int32_t C;          // columns per lane: 1, 2 or 4
+    int32_t R;          // rows per work item
+    int32_t nstrip, nseg;
+    int32_t vec;        // 1: all row starts 4C-byte aligned
+    int32_t slot;       // step slot of `part`
 };
-int adj_blocks_per_plane(int64_t h, int64_t w);
+int adj_strip_count(int W, int C);
+int adj_rows(int64_t n, int64_t h, int64_t w, int C);
+int64_t adj_items(int64_t n, int64_t h, int64_t w, int C);
 hipError_t launch_adjoint_step(const AdjArgs& a, hipStream_t st);
-hipError_t launch_lambda_reduce(const float* lam_part, int64_t n, int nblk, float* g_lam,
-                                hipStream_t st);
+hipError_t launch_lambda_reduce(const float* part, int steps, int64_t total, int64_t per_plane,
+                                int64_t n, float* g_lam, hipStream_t st);
 
 // Auxiliary kernels (wmc_aux.hip).
 hipError_t launch_fd(const float* u, float* out, int64_t n, int64_t h, int64_t w, int64_t ld,

@@ -27,13 +27,6 @@ namespace wmc {
 constexpr int kBlock = 256;                 // 4 independent waves per workgroup
 constexpr int kWavesPerBlock = kBlock / 64;
 
-// Maps blockIdx.x so that the blocks the hardware places on one XCD (it deals
-// blocks round-robin over the 8 XCDs) process one contiguous range of work
-// items: neighbouring strips then share halo rows in that XCD's L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
-    const int64_t q = G / 8, r = G % 8, x = b % 8;
-    return x * q + (x < r ? x : r) + b / 8;
-}
 
 template <int C>
 struct Pref {
@@ -84,17 +77,6 @@ struct Item {
     Coef k;
 };
 
-// Global memory access with a wave-uniform row pointer and a 32-bit per-lane
-// byte offset, so that the loads and stores use the scalar-base addressing
-// form (no 64-bit address arithmetic per lane).
-template <class V>
-__device__ __forceinline__ V ld_at(const float* row, uint32_t col) {
-    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(row) + col * 4u);
-}
-template <class V>
-__device__ __forceinline__ void st_at(float* row, uint32_t col, V v) {
-    *reinterpret_cast<V*>(reinterpret_cast<char*>(row) + col * 4u) = v;
-}
 
 // Runs one work item: rows of T sweeps pipelined in registers (see top of
 // file).  RCL: this strip holds the last image column (replicate clamp inside

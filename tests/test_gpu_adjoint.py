@@ -192,3 +192,30 @@ def test_c4_batch_against_oracle(wmc):
                                    noisy[b, 0].astype(np.float64), 1.0, 20, m_forced_all=maps[0])
         assert rel(g_f[b].cpu().numpy(), res["gf"] + res["gu0"]) <= 1e-4
         assert abs(float(g_lam[b]) - res["glam"]) <= 1e-4 * abs(res["glam"])
+
+
+@pytest.mark.parametrize("cols", ["1", "2", "4"])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (9, 1), (2, 3), (5, 60), (3, 61), (17, 62),
+                                   (33, 120), (70, 121), (40, 250), (129, 257)])
+def test_one_step_adjoint_shapes_and_lane_widths(wmc, monkeypatch, shape, cols):
+    """One adjoint step on shapes around the strip and segment boundaries of
+    every lane width (1, 2, 4 columns per lane), two planes, against the
+    oracle with the GPU's selection replayed: dL/dU, dL/df and dL/dlam."""
+    monkeypatch.setenv("WMC_ADJ_COLS", cols)
+    H, W = shape
+    rng = np.random.default_rng(H * 1000 + W)
+    u0 = rng.uniform(0, 1, size=(2, H, W))
+    fv = rng.uniform(0, 1, size=(2, H, W))
+    g = rng.standard_normal((2, H, W))
+    U0, F = to_gpu(u0), to_gpu(fv)
+    lam = torch.tensor([0.8, 2.0], device="cuda:0")
+    _, ck = wmc.solve(F, lam, 1, u0=U0, ckpt_every=1)
+    g_f, g_u0, g_lam = wmc.backward(to_gpu(g), F, lam, 1, ck, 1, u0=U0)
+    _, m = wmc.step(U0, F, lam, return_argmin=True)
+    m = m.cpu().numpy().astype(np.int8)
+    for p in range(2):
+        res = oracle.solve_adjoint(g[p], fv[p].astype(np.float32), float(lam[p]), 1,
+                                   u0=u0[p].astype(np.float32), m_forced_all=m[p][None])
+        assert rel(g_u0[p].cpu().numpy(), res["gu0"]) <= 1e-5
+        assert rel(g_f[p].cpu().numpy(), res["gf"]) <= 1e-5
+        assert abs(float(g_lam[p]) - res["glam"]) <= 1e-4 * max(abs(res["glam"]), 1e-6)
