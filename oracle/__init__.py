@@ -20,6 +20,9 @@ Curvature", arXiv 1903.07189):
   iteration of Sec. 5.3 (A = I).
 * :func:`fd_compute` / :func:`fd_flow` -- the conventional finite-difference
   discretisation of eq. (rhs) and its curvature flow (Sec. 5.4 comparator).
+* :func:`layer_forward` / :func:`layer_backward` -- the learnable half-window
+  layer of Sec. 4.3 (K learned 3x3 kernels, minimum-magnitude activation) and
+  its derivative with the selection held fixed.
 * :func:`listing` -- the Appendix A function's semantics (zero padding, true
   convolution, its candidate order).
 * :func:`step_adjoint` / :func:`solve_adjoint` -- derivative of the update map
@@ -81,6 +84,8 @@ def _load():
         lib.wmco_l1_solve.argtypes = [P, P, P, I64, I64, D, D, D, I, P, P]
         lib.wmco_fd_compute.argtypes = [P, I64, I64, D, P]
         lib.wmco_fd_flow.argtypes = [P, I64, I64, D, D, I, P]
+        lib.wmco_layer_forward.argtypes = [P, I64, I64, I, P, P, P]
+        lib.wmco_layer_backward.argtypes = [P, I64, I64, I, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -350,3 +355,32 @@ def fd_flow(u0, delta: float = 0.1, iters: int = 1, eps: float = 1e-12) -> np.nd
     out = np.empty_like(u0)
     _load().wmco_fd_flow(_p(u0), H, W, float(delta), float(eps), int(iters), _p(out))
     return out
+
+
+def layer_forward(U, w, return_argmin: bool = False):
+    """Learnable half-window layer (O12): K kernels w (K, 3, 3), min-|.|
+    activation.  Returns out (and the 0-based selection)."""
+    U = _d(U)
+    H, W = U.shape
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    K = w.shape[0]
+    if w.shape != (K, 3, 3) or not (1 <= K <= 127):
+        raise ValueError("w must be (K, 3, 3) with 1 <= K <= 127")
+    out = np.empty_like(U)
+    m = np.empty((H, W), dtype=np.int8)
+    _load().wmco_layer_forward(_p(U), H, W, K, _p(w), _p(out), _p(m))
+    return (out, m) if return_argmin else out
+
+
+def layer_backward(U, w, m, g):
+    """(gU, gW) of the layer with the selection m held fixed (O12)."""
+    U = _d(U)
+    H, W = U.shape
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    K = w.shape[0]
+    m = np.ascontiguousarray(m, dtype=np.int8)
+    g = _d(g)
+    gU = np.empty_like(U)
+    gW = np.empty((K, 3, 3))
+    _load().wmco_layer_backward(_p(U), H, W, K, _p(w), _p(m), _p(g), _p(gU), _p(gW))
+    return gU, gW

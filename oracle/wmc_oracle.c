@@ -33,7 +33,11 @@
  *       convolution, zero padding, its candidate order), for cross-checks;
  *   O10 the l1-fidelity primal-dual iteration of Sec. 5.3 (A = I);
  *   O11 the conventional finite-difference WMC of eq. (rhs) and its flow
- *       (the comparator of Sec. 5.4).
+ *       (the comparator of Sec. 5.4);
+ *   O12 the learnable half-window layer of Sec. 4.3: K learned 3x3 kernels
+ *       (eq. (conv) with the h_i replaced by learned weights) followed by the
+ *       minimum-magnitude activation of eq. (act), and its derivative with
+ *       respect to the input and the kernel weights.
  *
  * Images are row-major H x W arrays of doubles, x = column, y = row
  * (downwards).  Functions never allocate more than O(H W) scratch.
@@ -410,4 +414,51 @@ void wmco_fd_flow(const double* u0, int64_t H, int64_t W, double delta, double e
     memcpy(Uout, a, sizeof(double) * n);
     free(a);
     free(h);
+}
+
+/* O12: the learnable layer of Sec. 4.3.  d_k(x) = sum_o w_k[o] Ubar(x + o)
+ * for k = 0..K-1 (w: K x 3 x 3, [k][r][c] with r = 0 the row above, c = 0 the
+ * column to the left, like the printed kernels), m(x) = first k attaining
+ * min_k |d_k(x)| (eq. (act)), out(x) = d_m(x).  m_out (nullable) receives m. */
+void wmco_layer_forward(const double* U, int64_t H, int64_t W, int K, const double* w,
+                        double* out, int8_t* m_out) {
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) {
+            double best = 0.0;
+            int bi = 0;
+            for (int k = 0; k < K; ++k) {
+                double d = 0.0;
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c)
+                        d += w[(k * 3 + r) * 3 + c] * ubar(U, H, W, y + r - 1, x + c - 1);
+                if (k == 0 || fabs(d) < fabs(best)) {
+                    best = d;
+                    bi = k;
+                }
+            }
+            out[y * W + x] = best;
+            if (m_out) m_out[y * W + x] = (int8_t)bi;
+        }
+}
+
+/* O12: derivative of the layer with the selection m held fixed (the layer is
+ * linear in U and in w for a fixed m).  g = dL/dout.
+ *   gU(z)      = sum_{x, o : clamp(x + o) = z} w_{m(x)}[o] g(x)   (scatter)
+ *   gW_k[o]    = sum_{x : m(x) = k} g(x) Ubar(x + o)
+ * gU and gW (K x 3 x 3) are overwritten. */
+void wmco_layer_backward(const double* U, int64_t H, int64_t W, int K, const double* w,
+                         const int8_t* m, const double* g, double* gU, double* gW) {
+    memset(gU, 0, sizeof(double) * H * W);
+    memset(gW, 0, sizeof(double) * K * 9);
+    for (int64_t y = 0; y < H; ++y)
+        for (int64_t x = 0; x < W; ++x) {
+            const int k = m[y * W + x];
+            const double gv = g[y * W + x];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                    const int64_t zy = clampi(y + r - 1, 0, H - 1), zx = clampi(x + c - 1, 0, W - 1);
+                    gU[zy * W + zx] += w[(k * 3 + r) * 3 + c] * gv;
+                    gW[(k * 3 + r) * 3 + c] += gv * U[zy * W + zx];
+                }
+        }
 }

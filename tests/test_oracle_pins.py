@@ -805,3 +805,81 @@ def test_mcf_study_half_window_flow_keeps_straight_edges():
         assert s_hl > 0.99 and (1 - s_fd) > 5 * (1 - s_hl), (t, s_hl, s_fd)
         assert s_fd <= prev_fd + 1e-9 and s_hl <= prev_hl + 1e-9
         prev_hl, prev_fd = s_hl, s_fd
+
+
+# ---- learnable half-window layer (Sec. 4.3), O12 ------------------------------------
+
+def test_layer_with_printed_kernels_is_the_operator():
+    """With the eight printed kernels (x12, integer weights) the layer is the
+    Half Laplace Operator: on integer images every value is exact, so output
+    and selection (ties included) must match 12 * H_d bitwise."""
+    K12 = oracle.kernel_table().astype(np.float64)
+    rng = np.random.default_rng(31)
+    for shape in [(1, 1), (3, 1), (1, 4), (9, 13), (40, 33)]:
+        U = rng.integers(-20, 21, size=shape).astype(np.float64)
+        out, m = oracle.layer_forward(U, K12, return_argmin=True)
+        hd, mh = oracle.compute(U, return_argmin=True)
+        assert np.array_equal(out, 12 * hd)
+        assert np.array_equal(m, mh)
+
+
+def test_layer_single_kernel_is_a_correlation():
+    """K = 1: no selection, the layer is a correlation with replicate border
+    (scipy.ndimage.correlate, mode 'nearest')."""
+    from scipy import ndimage
+    rng = np.random.default_rng(32)
+    U = rng.uniform(-1, 1, size=(17, 23))
+    w = rng.uniform(-1, 1, size=(1, 3, 3))
+    ref = ndimage.correlate(U, w[0], mode="nearest")
+    assert np.allclose(oracle.layer_forward(U, w), ref, atol=1e-13)
+
+
+def _fixed_m_forward(U, w, m):
+    """The layer's map with the selection held at m, built from scipy
+    correlations (independent of the oracle's code)."""
+    from scipy import ndimage
+    resp = np.stack([ndimage.correlate(U, w[k], mode="nearest") for k in range(w.shape[0])])
+    return np.take_along_axis(resp, m[None].astype(np.int64), axis=0)[0]
+
+
+def test_layer_forward_selection_and_permutation():
+    rng = np.random.default_rng(33)
+    U = rng.uniform(0, 1, size=(25, 31))
+    w = rng.standard_normal((6, 3, 3))
+    out, m = oracle.layer_forward(U, w, return_argmin=True)
+    from scipy import ndimage
+    resp = np.stack([ndimage.correlate(U, w[k], mode="nearest") for k in range(6)])
+    assert np.array_equal(m, np.argmin(np.abs(resp), axis=0))   # first minimum
+    assert np.allclose(out, _fixed_m_forward(U, w, m), atol=1e-13)
+    perm = rng.permutation(6)
+    out2, m2 = oracle.layer_forward(U, w[perm], return_argmin=True)
+    assert np.allclose(out2, out, atol=1e-13)
+    assert np.array_equal(perm[m2], m)
+
+
+def test_layer_backward_dot_product_and_weight_fd():
+    """gU is the transpose of the fixed-selection map (dot-product test
+    against scipy correlations); gW matches central differences of
+    L = <g, out> in every weight (selections do not change for the step)."""
+    rng = np.random.default_rng(34)
+    H, W, K = 14, 19, 5
+    U = rng.uniform(0, 1, size=(H, W))
+    w = rng.standard_normal((K, 3, 3))
+    g = rng.standard_normal((H, W))
+    out, m = oracle.layer_forward(U, w, return_argmin=True)
+    gU, gW = oracle.layer_backward(U, w, m, g)
+    v = rng.standard_normal((H, W))
+    lhs = float(np.sum(_fixed_m_forward(v, w, m) * g))
+    assert abs(lhs - float(np.sum(v * gU))) <= 1e-12 * max(1.0, abs(lhs))
+    eps = 1e-6
+    for k in range(K):
+        for r in range(3):
+            for c in range(3):
+                wp, wm = w.copy(), w.copy()
+                wp[k, r, c] += eps
+                wm[k, r, c] -= eps
+                op, mp = oracle.layer_forward(U, wp, return_argmin=True)
+                om, mm = oracle.layer_forward(U, wm, return_argmin=True)
+                assert np.array_equal(mp, m) and np.array_equal(mm, m)
+                fd = (np.sum(g * op) - np.sum(g * om)) / (2 * eps)
+                assert abs(fd - gW[k, r, c]) <= 1e-6 * max(1.0, abs(gW[k, r, c]))
