@@ -212,6 +212,33 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
                  float* g_lam, void* ws, size_t ws_bytes, wmc_shape s, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The learnable half-window layer of Sec. 4.3: eq. (conv) with K learned 3x3
+ * kernels in place of the eight printed ones, followed by the minimum-
+ * magnitude activation of eq. (act):
+ *   d_k(x) = sum_o w[k][o] Ub(x + o)     (correlation, replicate border Ub)
+ *   sel(x) = first k attaining min_k |d_k(x)|,   out(x) = d_sel(x)(x).
+ * w: device, K x 3 x 3 floats, [k][row][col], row 0 = the image row above
+ * the pixel, col 0 = the column to its left (the printed kernels' layout);
+ * 1 <= K <= 16.  With the eight printed kernels times 12 the layer is 12 H_d.
+ * sel: uint8, same ld/ps layout as u (nullable in the forward; the backward
+ * needs the forward's).
+ *
+ * wmc_layer_backward -- derivative with the selection held fixed (the layer
+ * is linear in u and w for a fixed sel; ties are a null set):
+ *   g_u(z)     = sum_{x, o: clamp(x + o) = z} w[sel(x)][o] g_out(x)
+ *   g_w[k][o]  = sum_{x: sel(x) = k} g_out(x) Ub(x + o)
+ * g_u and g_w are overwritten (either may be NULL).  g_w is reduced in a
+ * fixed order: bitwise reproducible.  ws: wmc_layer_workspace(s, K) bytes
+ * when g_w is requested.
+ * ------------------------------------------------------------------------- */
+size_t wmc_layer_workspace(wmc_shape s, int K);
+int wmc_layer_forward(const float* u, const float* w, int K, float* out, uint8_t* sel,
+                      wmc_shape s, void* stream);
+int wmc_layer_backward(const float* u, const float* w, int K, const uint8_t* sel,
+                       const float* g_out, float* g_u, float* g_w, void* ws, size_t ws_bytes,
+                       wmc_shape s, void* stream);
+
+/* ---------------------------------------------------------------------------
  * wmc_fd_compute -- the conventional discretisation of the continuous WMC of
  * eq. (rhs), H^w = Lap U - (U_y^2 U_yy + 2 U_x U_y U_xy + U_x^2 U_xx) /
  * (U_x^2 + U_y^2 + eps), with second-order central differences at unit

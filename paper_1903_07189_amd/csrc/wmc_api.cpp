@@ -1357,6 +1357,62 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     return WMC_OK;
 }
 
+size_t wmc_layer_workspace(wmc_shape s, int K) {
+    if (check_shape(s) || K < 1 || K > 16) return 0;
+    int R, ns, nsg;
+    const int64_t items = layer_bwd_items(s.n, s.h, s.w, &R, &ns, &nsg);
+    return (size_t)items * 9 * (size_t)K * sizeof(float);
+}
+
+int wmc_layer_forward(const float* u, const float* w, int K, float* out, uint8_t* sel,
+                      wmc_shape s, void* stream) {
+    g_err.clear();
+    int rc = check_shape(s);
+    if (rc) return rc;
+    if (!u || !w || !out) return fail(WMC_EINVAL, "wmc_layer_forward: null pointer");
+    if (K < 1 || K > 16) return fail(WMC_EINVAL, "wmc_layer_forward: K must be in [1, 16]");
+    const int64_t ext = extent_elems(s);
+    const Range ro = range_of(out, ext, 4), ru = range_of(u, ext, 4), rs = range_of(sel, ext, 1);
+    if (overlaps(ro, ru) || overlaps(rs, ru) || overlaps(rs, ro) ||
+        overlaps(range_of(w, 9 * K, 4), ro) || overlaps(range_of(w, 9 * K, 4), rs))
+        return fail(WMC_EINVAL, "wmc_layer_forward: buffers overlap");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    const hipError_t e = launch_layer_forward(u, w, K, out, sel, s.n, s.h, s.w, s.ld, s.ps,
+                                              as_stream(stream));
+    return e == hipSuccess ? WMC_OK : hip_fail(e, "wmc_layer_forward launch");
+}
+
+int wmc_layer_backward(const float* u, const float* w, int K, const uint8_t* sel,
+                       const float* g_out, float* g_u, float* g_w, void* ws, size_t ws_bytes,
+                       wmc_shape s, void* stream) {
+    g_err.clear();
+    int rc = check_shape(s);
+    if (rc) return rc;
+    if (!u || !w || !sel || !g_out) return fail(WMC_EINVAL, "wmc_layer_backward: null pointer");
+    if (K < 1 || K > 16) return fail(WMC_EINVAL, "wmc_layer_backward: K must be in [1, 16]");
+    if (!g_u && !g_w) return WMC_OK;
+    const size_t need = wmc_layer_workspace(s, K);
+    if (g_w && (!ws || ws_bytes < need))
+        return fail(WMC_ENOMEM, "wmc_layer_backward: workspace smaller than wmc_layer_workspace()");
+    const int64_t ext = extent_elems(s);
+    const Range rgu = range_of(g_u, ext, 4), rgw = range_of(g_w, 9 * K, 4);
+    const Range rws = range_of(g_w ? ws : nullptr, (int64_t)need, 1);
+    for (const Range& r : {range_of(u, ext, 4), range_of(g_out, ext, 4), range_of(sel, ext, 1),
+                           range_of(w, 9 * K, 4)})
+        if (overlaps(r, rgu) || overlaps(r, rgw) || overlaps(r, rws))
+            return fail(WMC_EINVAL, "wmc_layer_backward: outputs overlap inputs");
+    if (overlaps(rgu, rgw) || overlaps(rgu, rws) || overlaps(rgw, rws))
+        return fail(WMC_EINVAL, "wmc_layer_backward: outputs overlap each other or the workspace");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    const hipError_t e = launch_layer_backward(u, w, K, sel, g_out, g_u, static_cast<float*>(ws),
+                                               g_w, s.n, s.h, s.w, s.ld, s.ps, as_stream(stream));
+    return e == hipSuccess ? WMC_OK : hip_fail(e, "wmc_layer_backward launch");
+}
+
 int wmc_fd_compute(const float* u, float* hw, float eps, wmc_shape s, void* stream) {
     g_err.clear();
     int rc = check_shape(s);

@@ -104,6 +104,15 @@ hipError_t launch_adjoint_step(const AdjArgs& a, hipStream_t st);
 hipError_t launch_lambda_reduce(const float* part, int steps, int64_t total, int64_t per_plane,
                                 int64_t n, float* g_lam, hipStream_t st);
 
+// Learnable half-window layer (wmc_layer.hip).
+int64_t layer_bwd_items(int64_t n, int64_t h, int64_t w, int* R, int* nstrip, int* nseg);
+hipError_t launch_layer_forward(const float* u, const float* w, int K, float* out, uint8_t* sel,
+                                int64_t n, int64_t h, int64_t wd, int64_t ld, int64_t ps,
+                                hipStream_t st);
+hipError_t launch_layer_backward(const float* u, const float* w, int K, const uint8_t* sel,
+                                 const float* g, float* g_u, float* part, float* g_w, int64_t n,
+                                 int64_t h, int64_t wd, int64_t ld, int64_t ps, hipStream_t st);
+
 // Auxiliary kernels (wmc_aux.hip).
 hipError_t launch_fd(const float* u, float* out, int64_t n, int64_t h, int64_t w, int64_t ld,
                      int64_t ps, float dt, float eps, bool flow, hipStream_t st);

@@ -1,0 +1,367 @@
+// wmc_layer.hip -- the learnable half-window layer of Sec. 4.3 for gfx950.
+//
+// Forward: K learned 3x3 kernels w_k (K <= 16) correlated with the
+// replicate-padded input, then the minimum-magnitude activation of eq. (act):
+//   d_k(x) = sum_o w_k[o] Ub(x + o),  m(x) = first k with min |d_k(x)|,
+//   out(x) = d_m(x).
+// With the eight printed kernels this is the Half Laplace Operator (times 12
+// for the integer kernel table).
+//
+// Backward, with the selection held fixed (the layer is linear in U and in w
+// for a fixed m):
+//   gU(z)   = sum_{x, o: clamp(x + o) = z} w_{m(x)}[o] g(x)
+//   gW_k[o] = sum_{x: m(x) = k} g(x) Ub(x + o).
+//
+// Both kernels stream rows with one wave per work item (a strip of 64
+// columns, one column per lane, and a segment of R rows); horizontal
+// neighbours come from the adjacent lanes by DPP.  Loads use clamped row and
+// column indices, so the lanes and rows beyond the image carry the replicate
+// border.  The backward's strips have a two-column halo on each side; the
+// first and last hold the virtual columns -1 and W, where the scatter of the
+// border pixels lands, and fold them (and the virtual rows -1 and H) back
+// onto the border.  gW: every lane accumulates its own products in a private
+// slice of LDS indexed by (kernel, tap); a fixed-order reduction over lanes,
+// then over work items, makes the result bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "wmc_device.hpp"
+#include "wmc_internal.h"
+
+#include <algorithm>
+
+namespace wmc {
+
+constexpr int kLayerMaxK = 16;
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+struct LayerFwdArgs {
+    const float* u;
+    const float* w;  // K x 3 x 3
+    float* out;
+    uint8_t* sel;    // may be null
+    int64_t n, h, w_, ld, ps;
+    int32_t K, R, nstrip, nseg;
+};
+
+constexpr int kFwdHalo = 1;
+constexpr int kFwdStep = 64 - 2 * kFwdHalo;
+
+__global__ __launch_bounds__(256) void k_layer_fwd(LayerFwdArgs A) {
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t per_plane = (int64_t)A.nseg * A.nstrip;
+    const int64_t total = A.n * per_plane;
+    const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
+    if (item >= total) return;
+    const int p = (int)(item / per_plane);
+    const int rem = (int)(item - (int64_t)p * per_plane);
+    const int seg = rem / A.nstrip;
+    const int strip = rem - seg * A.nstrip;
+    const int H = (int)A.h, W = (int)A.w_;
+    const int x = strip * kFwdStep - kFwdHalo + lane;
+    const int ox1 = strip * kFwdStep + kFwdStep < W ? strip * kFwdStep + kFwdStep : W;
+    const bool own = x >= strip * kFwdStep && x < ox1;
+    const uint32_t xc = (uint32_t)(x < 0 ? 0 : (x < W ? x : W - 1));
+    const int y0 = seg * A.R;
+    const int y1 = y0 + A.R < H ? y0 + A.R : H;
+    const float* u = A.u + (int64_t)p * A.ps;
+    float* out = A.out + (int64_t)p * A.ps;
+    uint8_t* sel = A.sel ? A.sel + (int64_t)p * A.ps : nullptr;
+
+    // rows y-1, y, y+1: the lane's column and its two neighbours
+    float v[3][3];
+    float pre[2];
+    auto row_val = [&](int r) {
+        const int rr = r < 0 ? 0 : (r < H ? r : H - 1);
+        return ld_at<float>(u + (int64_t)rr * A.ld, xc);
+    };
+    auto put = [&](float (&d)[3], float c) {
+        d[0] = from_lower_lane(c, c);
+        d[1] = c;
+        d[2] = from_upper_lane(c, c);
+    };
+    put(v[0], row_val(y0 - 1));
+    put(v[1], row_val(y0));
+    pre[0] = row_val(y0 + 1);
+    pre[1] = row_val(y0 + 2);
+    for (int y = y0; y < y1; ++y) {
+        put(v[2], pre[0]);
+        pre[0] = pre[1];
+        pre[1] = row_val(y + 3);
+        float best = 0.0f;
+        int bi = 0;
+        for (int k = 0; k < A.K; ++k) {
+            const float* wk = A.w + 9 * k;
+            float d = wk[0] * v[0][0];
+#pragma unroll
+            for (int t = 1; t < 9; ++t) d = __builtin_fmaf(wk[t], v[t / 3][t % 3], d);
+            if (k == 0 || __builtin_fabsf(d) < __builtin_fabsf(best)) {
+                best = d;
+                bi = k;
+            }
+        }
+        if (own) {
+            out[(int64_t)y * A.ld + x] = best;
+            if (sel) sel[(int64_t)y * A.ld + x] = (uint8_t)bi;
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            v[0][j] = v[1][j];
+            v[1][j] = v[2][j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+struct LayerBwdArgs {
+    const float* u;
+    const float* w;
+    const uint8_t* sel;
+    const float* g;
+    float* g_u;      // may be null
+    float* part;     // K*9 partial sums of gW per work item, or null
+    int64_t n, h, w_, ld, ps;
+    int32_t K, R, nstrip, nseg;
+};
+
+constexpr int kBwdHalo = 2;
+constexpr int kBwdStep = 64 - 2 * kBwdHalo;
+
+// One wave per block; dynamic LDS: weights (K*9) then the per-lane
+// accumulators [K*9][64].
+__global__ __launch_bounds__(64) void k_layer_bwd(LayerBwdArgs A) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x;
+    const int64_t per_plane = (int64_t)A.nseg * A.nstrip;
+    const int64_t total = A.n * per_plane;
+    const int64_t item = xcd_remap(blockIdx.x, gridDim.x);
+    if (item >= total) return;
+    const int K = A.K, KT = 9 * A.K;
+    float* wt = lds;
+    float* acc = lds + KT;
+    for (int i = lane; i < KT; i += 64) wt[i] = A.w[i];
+    if (A.part)
+        for (int i = 0; i < KT; ++i) acc[i * 64 + lane] = 0.0f;
+    __syncthreads();
+
+    const int p = (int)(item / per_plane);
+    const int rem = (int)(item - (int64_t)p * per_plane);
+    const int seg = rem / A.nstrip;
+    const int strip = rem - seg * A.nstrip;
+    const int H = (int)A.h, W = (int)A.w_;
+    const int x = strip * kBwdStep - kBwdHalo + lane;
+    const int ox0 = strip * kBwdStep;
+    const int ox1 = ox0 + kBwdStep < W ? ox0 + kBwdStep : W;
+    const bool own = x >= ox0 && x < ox1;
+    const bool inimg = x >= 0 && x < W;
+    const bool isL = x == 0, isR = x == W - 1;
+    const bool edge = (strip * kBwdStep - kBwdHalo) < 0 || (strip * kBwdStep - kBwdHalo + 64) > W;
+    const uint32_t xc = (uint32_t)(x < 0 ? 0 : (x < W ? x : W - 1));
+    const int y0 = seg * A.R;
+    const int y1 = y0 + A.R < H ? y0 + A.R : H;
+    const int64_t off = (int64_t)p * A.ps;
+    const float* u = A.u + off;
+    const float* g = A.g + off;
+    const uint8_t* sel = A.sel + off;
+    float* gu = A.g_u ? A.g_u + off : nullptr;
+
+    // window rows rho-1, rho, rho+1: U with neighbours (replicate), g and m
+    // with neighbours (g = 0 outside the image)
+    float uv[3][3], gv[3][3];
+    int mv[3][3];
+    struct Pre {
+        float u, g;
+        int m;
+    } pre[2];
+    auto fetch = [&](int r) {
+        Pre q;
+        const int rr = r < 0 ? 0 : (r < H ? r : H - 1);
+        q.u = ld_at<float>(u + (int64_t)rr * A.ld, xc);
+        const bool in = inimg && r >= 0 && r < H;
+        q.g = in ? ld_at<float>(g + (int64_t)rr * A.ld, xc) : 0.0f;
+        q.m = in ? (int)sel[(int64_t)rr * A.ld + xc] : 0;
+        if (q.m >= K) q.m = K - 1;  // defensive: never index past the table
+        return q;
+    };
+    auto put = [&](int j, const Pre& q) {
+        uv[j][0] = from_lower_lane(q.u, q.u);
+        uv[j][1] = q.u;
+        uv[j][2] = from_upper_lane(q.u, q.u);
+        gv[j][0] = from_lower_lane(0.0f, q.g);
+        gv[j][1] = q.g;
+        gv[j][2] = from_upper_lane(0.0f, q.g);
+        mv[j][0] = __builtin_amdgcn_update_dpp(0, q.m, 0x138, 0xF, 0xF, false);
+        mv[j][1] = q.m;
+        mv[j][2] = __builtin_amdgcn_update_dpp(0, q.m, 0x130, 0xF, 0xF, false);
+    };
+    put(0, fetch(y0 - 2));
+    put(1, fetch(y0 - 1));
+    pre[0] = fetch(y0);
+    pre[1] = fetch(y0 + 1);
+    float topfold = 0.0f, pend = 0.0f;
+    // rows rho = y0-1 .. y1 (the virtual rows -1 and H only at the image border)
+    for (int rho = y0 - 1; rho <= y1; ++rho) {
+        // window rows 0, 1 hold rho-1, rho; row rho+1 comes from the prefetch
+        put(2, pre[0]);
+        pre[0] = pre[1];
+        pre[1] = fetch(rho + 3);
+
+        const bool owned_row = rho >= y0 && rho < y1;
+        const bool top = rho == -1 && y0 == 0;
+        const bool bot = rho == H && y1 == H;
+        if (owned_row || top || bot) {
+            if (gu) {
+                // gU at (rho, x): neighbour (dy, dx) contributes w_{m}[(1-dy, 1-dx)] g
+                float a = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        a = __builtin_fmaf(wt[mv[i][j] * 9 + (2 - i) * 3 + (2 - j)], gv[i][j], a);
+                if (edge) {
+                    // column ring: virtual column -1 onto 0, W onto W-1
+                    const float l = from_lower_lane(0.0f, a);
+                    const float r = from_upper_lane(0.0f, a);
+                    a += (isL ? l : 0.0f) + (isR ? r : 0.0f);
+                }
+                if (top) {
+                    topfold = a;
+                } else if (bot) {
+                    if (gu && own) gu[(int64_t)(H - 1) * A.ld + x] = a + pend;
+                } else {
+                    if (rho == 0) a += topfold;
+                    if (rho == H - 1) pend = a;
+                    else if (gu && own) gu[(int64_t)rho * A.ld + x] = a;
+                }
+            }
+            if (A.part && owned_row && own) {
+                const float gc = gv[1][1];
+                const int base = mv[1][1] * 9;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    float* q = acc + (base + t) * 64 + lane;
+                    *q = __builtin_fmaf(gc, uv[t / 3][t % 3], *q);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            uv[0][j] = uv[1][j]; uv[1][j] = uv[2][j];
+            gv[0][j] = gv[1][j]; gv[1][j] = gv[2][j];
+            mv[0][j] = mv[1][j]; mv[1][j] = mv[2][j];
+        }
+    }
+    if (A.part) {
+        // fixed-order butterfly over the lanes of each (kernel, tap)
+        __syncthreads();
+        for (int e = 0; e < KT; ++e) {
+            float s = acc[e * 64 + lane];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+            if (lane == 0) A.part[item * KT + e] = s;
+        }
+    }
+}
+
+// gW[e] = sum over work items of part[item][e], in item order.
+__global__ __launch_bounds__(256) void k_layer_wreduce(const float* __restrict__ part,
+                                                       int64_t items, int KT,
+                                                       float* __restrict__ gw) {
+    const int e = blockIdx.x;
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int64_t i = threadIdx.x; i < items; i += 256) s += part[i * KT + e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gw[e] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static int layer_rows(int64_t n, int64_t h, int64_t strips) {
+    const int64_t rows_total = n * h * strips;
+    int R = 16;
+    while (R < 256 && rows_total / R > 8192) R *= 2;
+    return R;
+}
+
+int layer_fwd_items(int64_t n, int64_t h, int64_t w, int* R, int* nstrip, int* nseg) {
+    *nstrip = (int)((w + kFwdStep - 1) / kFwdStep);
+    *R = layer_rows(n, h, *nstrip);
+    *nseg = seg_count((int)h, *R);
+    return (int)std::min<int64_t>(n * (int64_t)(*nstrip) * (*nseg), 0x7fffffff);
+}
+
+int64_t layer_bwd_items(int64_t n, int64_t h, int64_t w, int* R, int* nstrip, int* nseg) {
+    *nstrip = (int)((w + kBwdStep - 1) / kBwdStep);
+    *R = layer_rows(n, h, *nstrip);
+    *nseg = seg_count((int)h, *R);
+    return n * (int64_t)(*nstrip) * (*nseg);
+}
+
+hipError_t launch_layer_forward(const float* u, const float* w, int K, float* out, uint8_t* sel,
+                                int64_t n, int64_t h, int64_t wd, int64_t ld, int64_t ps,
+                                hipStream_t st) {
+    if (K < 1 || K > kLayerMaxK) return hipErrorInvalidValue;
+    LayerFwdArgs a{};
+    a.u = u;
+    a.w = w;
+    a.out = out;
+    a.sel = sel;
+    a.n = n;
+    a.h = h;
+    a.w_ = wd;
+    a.ld = ld;
+    a.ps = ps;
+    a.K = K;
+    int R, ns, nsg;
+    layer_fwd_items(n, h, wd, &R, &ns, &nsg);
+    a.R = R;
+    a.nstrip = ns;
+    a.nseg = nsg;
+    const int64_t total = n * (int64_t)ns * nsg;
+    hipLaunchKernelGGL(k_layer_fwd, dim3((unsigned)((total + 3) / 4)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_layer_backward(const float* u, const float* w, int K, const uint8_t* sel,
+                                 const float* g, float* g_u, float* part, float* g_w, int64_t n,
+                                 int64_t h, int64_t wd, int64_t ld, int64_t ps, hipStream_t st) {
+    if (K < 1 || K > kLayerMaxK) return hipErrorInvalidValue;
+    LayerBwdArgs a{};
+    a.u = u;
+    a.w = w;
+    a.sel = sel;
+    a.g = g;
+    a.g_u = g_u;
+    a.part = g_w ? part : nullptr;
+    a.n = n;
+    a.h = h;
+    a.w_ = wd;
+    a.ld = ld;
+    a.ps = ps;
+    a.K = K;
+    int R, ns, nsg;
+    const int64_t items = layer_bwd_items(n, h, wd, &R, &ns, &nsg);
+    a.R = R;
+    a.nstrip = ns;
+    a.nseg = nsg;
+    const size_t lds = (size_t)(9 * K) * sizeof(float) * (g_w ? 65 : 1);
+    hipLaunchKernelGGL(k_layer_bwd, dim3((unsigned)items), dim3(64), lds, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !g_w) return e;
+    hipLaunchKernelGGL(k_layer_wreduce, dim3((unsigned)(9 * K)), dim3(256), 0, st, part, items,
+                       9 * K, g_w);
+    return hipGetLastError();
+}
+
+}  // namespace wmc

@@ -48,7 +48,8 @@ class Tuning(ctypes.Structure):
 _lib = None
 EXPORTS = ["wmc_compute", "wmc_step", "wmc_solve_workspace", "wmc_set_stride",
            "wmc_num_checkpoints", "wmc_solve", "wmc_solve_tuning", "wmc_l1_workspace",
-           "wmc_solve_l1", "wmc_fd_compute", "wmc_fd_flow",
+           "wmc_solve_l1", "wmc_fd_compute", "wmc_fd_flow", "wmc_layer_workspace",
+           "wmc_layer_forward", "wmc_layer_backward",
            "wmc_batched_workspace", "wmc_solve_batched", "wmc_autotune", "wmc_backward_workspace",
            "wmc_backward", "wmc_selftest", "wmc_last_error", "wmc_release"]
 
@@ -78,6 +79,10 @@ def lib():
     L.wmc_solve_l1.argtypes = [P, P, P, P, P, P, F, I, F, ctypes.POINTER(Tuning), P, SZ, Shape, P]
     L.wmc_fd_compute.argtypes = [P, P, F, Shape, P]
     L.wmc_fd_flow.argtypes = [P, P, I, F, F, P, SZ, Shape, P]
+    L.wmc_layer_workspace.argtypes = [Shape, I]
+    L.wmc_layer_workspace.restype = SZ
+    L.wmc_layer_forward.argtypes = [P, P, I, P, P, Shape, P]
+    L.wmc_layer_backward.argtypes = [P, P, I, P, P, P, P, P, SZ, Shape, P]
     L.wmc_batched_workspace.argtypes = [ctypes.POINTER(Image), I]
     L.wmc_batched_workspace.restype = SZ
     L.wmc_solve_batched.argtypes = [ctypes.POINTER(Image), I, P, I, F, ctypes.POINTER(Tuning), P,
@@ -92,7 +97,7 @@ def lib():
     L.wmc_release.argtypes = []
     L.wmc_release.restype = None
     for name in ("wmc_compute", "wmc_step", "wmc_solve", "wmc_solve_tuning", "wmc_solve_l1",
-                 "wmc_fd_compute", "wmc_fd_flow",
+                 "wmc_fd_compute", "wmc_fd_flow", "wmc_layer_forward", "wmc_layer_backward",
                  "wmc_solve_batched",
                  "wmc_autotune",
                  "wmc_backward", "wmc_selftest"):
@@ -263,6 +268,71 @@ def fd_flow(u0: torch.Tensor, iters: int, dt: float = 0.1, eps: float = 1e-12) -
     check(L.wmc_fd_flow(_ptr(u0), _ptr(out), int(iters), float(dt), float(eps), _ptr(ws),
                         ws.numel() * 4, s, _stream()))
     return out[0] if squeeze else out
+
+
+def _weights(w: torch.Tensor) -> torch.Tensor:
+    if w.dim() != 3 or tuple(w.shape[1:]) != (3, 3):
+        raise ValueError("kernels must be a (K, 3, 3) tensor")
+    if not (1 <= w.shape[0] <= 16):
+        raise ValueError("1 <= K <= 16 kernels")
+    return w.detach().to(dtype=torch.float32).contiguous()
+
+
+def layer_forward(u: torch.Tensor, w: torch.Tensor):
+    """Learnable half-window layer (Sec. 4.3): K kernels w (K, 3, 3), then the
+    minimum-magnitude activation.  Returns (out, sel) with sel uint8."""
+    squeeze = u.dim() == 2
+    u = _planes(u).contiguous()
+    wt = _weights(w)
+    out = torch.empty_like(u)
+    sel = torch.empty(u.shape, dtype=torch.uint8, device=u.device)
+    check(lib().wmc_layer_forward(_ptr(u), _ptr(wt), wt.shape[0], _ptr(out), _ptr(sel),
+                                  shape_of(u), _stream()))
+    return (out[0], sel[0]) if squeeze else (out, sel)
+
+
+def layer_backward(u: torch.Tensor, w: torch.Tensor, sel: torch.Tensor, g: torch.Tensor,
+                   need_u: bool = True, need_w: bool = True):
+    """(g_u, g_w) of the layer with the selection held fixed."""
+    squeeze = u.dim() == 2
+    u = _planes(u).contiguous()
+    sel = (sel.unsqueeze(0) if sel.dim() == 2 else sel).contiguous()
+    g = _planes(g).contiguous()
+    if sel.shape != u.shape or g.shape != u.shape or sel.dtype != torch.uint8:
+        raise ValueError("sel (uint8) and g must have u's shape")
+    wt = _weights(w)
+    K = wt.shape[0]
+    s = shape_of(u)
+    L = lib()
+    g_u = torch.empty_like(u) if need_u else None
+    g_w = torch.empty((K, 3, 3), dtype=torch.float32, device=u.device) if need_w else None
+    ws = torch.empty(max(1, L.wmc_layer_workspace(s, K) // 4), dtype=torch.float32,
+                     device=u.device) if need_w else None
+    check(L.wmc_layer_backward(_ptr(u), _ptr(wt), K, _ptr(sel), _ptr(g), _ptr(g_u), _ptr(g_w),
+                               _ptr(ws), 0 if ws is None else ws.numel() * 4, s, _stream()))
+    if squeeze and g_u is not None:
+        g_u = g_u[0]
+    return g_u, g_w
+
+
+class WMCKernelLayer(torch.autograd.Function):
+    """out = layer(u; w) as a differentiable op: gradients to u (N, H, W) and to
+    the kernels w (K, 3, 3), with the forward's selection held fixed."""
+
+    @staticmethod
+    def forward(ctx, u, w):
+        out, sel = layer_forward(u.detach(), w)
+        ctx.save_for_backward(u.detach(), w.detach(), sel)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        u, w, sel = ctx.saved_tensors
+        g_u, g_w = layer_backward(u, w, sel, g.contiguous(), need_u=ctx.needs_input_grad[0],
+                                  need_w=ctx.needs_input_grad[1])
+        if g_w is not None:
+            g_w = g_w.to(w.dtype)
+        return g_u, g_w
 
 
 def solve_tuning(f: torch.Tensor | None, lam=1.0, dt: float = 0.0, u0: torch.Tensor | None = None):
