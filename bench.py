@@ -321,6 +321,18 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side):
                            "backward_gpx_step_s": round(pxs / ((ms_t - ms_f) * 1e-3) / 1e9, 1),
                            "note": "backward = segment recompute + adjoint steps + lam reduction"}
     del x
+    # learnable half-window layer, 8 kernels, on the 16 x 512^2 batch
+    xw = torch.from_numpy(wmc_synth.c4()[0][:, 0]).to(f.device)
+    kw = wmc.nn.printed_kernels(device=f.device)
+    out_l, sel_l = wmc.layer_forward(xw, kw)
+    gl = torch.randn_like(xw)
+    ms_lf = timed(lambda: wmc.layer_forward(xw, kw), 10, stream, torch) / 10
+    ms_lb = timed(lambda: wmc.layer_backward(xw, kw, sel_l, gl), 10, stream, torch) / 10
+    npx = xw.numel()
+    ex["layer_k8_16x512"] = {"forward_gpx_s": round(npx / (ms_lf * 1e-3) / 1e9, 1),
+                             "backward_gpx_s": round(npx / (ms_lb * 1e-3) / 1e9, 1),
+                             "ms_forward": round(ms_lf, 4), "ms_backward": round(ms_lb, 4)}
+    del xw, out_l, sel_l, gl
     # uneven batch: 64 images x 3 channels, sides U{128..2048}, 100 iterations
     sizes = wmc_synth.c3_sizes()
     imgs = []

@@ -5,11 +5,12 @@ Jacobi iterations (Sec. 3.5, Sec. 5.2) -- runs in hand-written HIP kernels for
 gfx950 behind the C ABI of include/wmc.h (libwmc.so).  This package is the
 thin Python binding of that ABI; see :mod:`paper_1903_07189_amd.wmc`.
 """
+from . import nn
 from .wmc import (WMCError, WMCKernelLayer, WMCSolve, SolveBatchedPlan, SolvePlan, autotune,
                   backward, compute, fd_compute, fd_flow, layer_backward, layer_forward, lib,
                   release, selftest, shape_of, solve, solve_batched, solve_l1, solve_tuning, step)
 
 __all__ = ["WMCError", "WMCKernelLayer", "WMCSolve", "SolveBatchedPlan", "SolvePlan", "autotune",
            "backward", "compute", "fd_compute", "fd_flow", "layer_backward", "layer_forward",
-           "lib", "release", "selftest", "shape_of", "solve", "solve_batched", "solve_l1",
+           "lib", "nn", "release", "selftest", "shape_of", "solve", "solve_batched", "solve_l1",
            "solve_tuning", "step"]
