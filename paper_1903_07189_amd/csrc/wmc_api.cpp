@@ -1359,9 +1359,7 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
 
 size_t wmc_layer_workspace(wmc_shape s, int K) {
     if (check_shape(s) || K < 1 || K > 16) return 0;
-    int R, ns, nsg;
-    const int64_t items = layer_bwd_items(s.n, s.h, s.w, &R, &ns, &nsg);
-    return (size_t)items * 9 * (size_t)K * sizeof(float);
+    return (size_t)layer_part_floats(s.n, s.h, s.w, K) * sizeof(float);
 }
 
 int wmc_layer_forward(const float* u, const float* w, int K, float* out, uint8_t* sel,

@@ -105,7 +105,7 @@ hipError_t launch_lambda_reduce(const float* part, int steps, int64_t total, int
                                 int64_t n, float* g_lam, hipStream_t st);
 
 // Learnable half-window layer (wmc_layer.hip).
-int64_t layer_bwd_items(int64_t n, int64_t h, int64_t w, int* R, int* nstrip, int* nseg);
+int64_t layer_part_floats(int64_t n, int64_t h, int64_t w, int K);
 hipError_t launch_layer_forward(const float* u, const float* w, int K, float* out, uint8_t* sel,
                                 int64_t n, int64_t h, int64_t wd, int64_t ld, int64_t ps,
                                 hipStream_t st);

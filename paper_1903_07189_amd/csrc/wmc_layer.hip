@@ -45,10 +45,20 @@ struct LayerFwdArgs {
     int32_t K, R, nstrip, nseg;
 };
 
-constexpr int kFwdHalo = 1;
-constexpr int kFwdStep = 64 - 2 * kFwdHalo;
+constexpr int kFwdC = 2;                           // columns per lane
+constexpr int kFwdHalo = kFwdC;                    // one column, rounded up to whole lanes
+constexpr int kFwdStep = 64 * kFwdC - 2 * kFwdHalo;
 
+// KT > 0: exactly KT kernels, weights held in scalar registers for the whole
+// work item.  KT == 0: any K <= 16, weights read from an LDS copy.
+template <int KT>
 __global__ __launch_bounds__(256) void k_layer_fwd(LayerFwdArgs A) {
+    constexpr int C = kFwdC;
+    __shared__ float wl[KT == 0 ? 9 * kLayerMaxK : 1];
+    if constexpr (KT == 0) {
+        for (int i = threadIdx.x; i < 9 * A.K; i += 256) wl[i] = A.w[i];
+        __syncthreads();
+    }
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int64_t per_plane = (int64_t)A.nseg * A.nstrip;
@@ -60,54 +70,92 @@ __global__ __launch_bounds__(256) void k_layer_fwd(LayerFwdArgs A) {
     const int seg = rem / A.nstrip;
     const int strip = rem - seg * A.nstrip;
     const int H = (int)A.h, W = (int)A.w_;
-    const int x = strip * kFwdStep - kFwdHalo + lane;
-    const int ox1 = strip * kFwdStep + kFwdStep < W ? strip * kFwdStep + kFwdStep : W;
-    const bool own = x >= strip * kFwdStep && x < ox1;
-    const uint32_t xc = (uint32_t)(x < 0 ? 0 : (x < W ? x : W - 1));
+    const int xb = strip * kFwdStep - kFwdHalo + C * lane;
+    const int ox0 = strip * kFwdStep;
+    const int ox1 = ox0 + kFwdStep < W ? ox0 + kFwdStep : W;
+    bool own[C];
+    uint32_t xc[C];
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        const int x = xb + e;
+        own[e] = x >= ox0 && x < ox1;
+        xc[e] = (uint32_t)(x < 0 ? 0 : (x < W ? x : W - 1));
+    }
     const int y0 = seg * A.R;
     const int y1 = y0 + A.R < H ? y0 + A.R : H;
     const float* u = A.u + (int64_t)p * A.ps;
     float* out = A.out + (int64_t)p * A.ps;
     uint8_t* sel = A.sel ? A.sel + (int64_t)p * A.ps : nullptr;
 
-    // rows y-1, y, y+1: the lane's column and its two neighbours
-    float v[3][3];
-    float pre[2];
-    auto row_val = [&](int r) {
+    float wr[KT > 0 ? 9 * KT : 1];
+    if constexpr (KT > 0) {
+#pragma unroll
+        for (int i = 0; i < 9 * KT; ++i) wr[i] = A.w[i];
+    }
+
+    // rows y-1, y, y+1: the lane's C columns with one neighbour on each side
+    float v[3][C + 2];
+    float pre[2][C];
+    auto fetch = [&](float (&d)[C], int r) {
         const int rr = r < 0 ? 0 : (r < H ? r : H - 1);
-        return ld_at<float>(u + (int64_t)rr * A.ld, xc);
+        const float* rp = u + (int64_t)rr * A.ld;
+#pragma unroll
+        for (int e = 0; e < C; ++e) d[e] = ld_at<float>(rp, xc[e]);
     };
-    auto put = [&](float (&d)[3], float c) {
-        d[0] = from_lower_lane(c, c);
-        d[1] = c;
-        d[2] = from_upper_lane(c, c);
+    auto put = [&](float (&d)[C + 2], const float (&c)[C]) {
+        d[0] = from_lower_lane(c[0], c[C - 1]);
+#pragma unroll
+        for (int e = 0; e < C; ++e) d[e + 1] = c[e];
+        d[C + 1] = from_upper_lane(c[C - 1], c[0]);
     };
-    put(v[0], row_val(y0 - 1));
-    put(v[1], row_val(y0));
-    pre[0] = row_val(y0 + 1);
-    pre[1] = row_val(y0 + 2);
+    {
+        float t[C];
+        fetch(t, y0 - 1);
+        put(v[0], t);
+        fetch(t, y0);
+        put(v[1], t);
+    }
+    fetch(pre[0], y0 + 1);
+    fetch(pre[1], y0 + 2);
     for (int y = y0; y < y1; ++y) {
         put(v[2], pre[0]);
-        pre[0] = pre[1];
-        pre[1] = row_val(y + 3);
-        float best = 0.0f;
-        int bi = 0;
-        for (int k = 0; k < A.K; ++k) {
-            const float* wk = A.w + 9 * k;
-            float d = wk[0] * v[0][0];
 #pragma unroll
-            for (int t = 1; t < 9; ++t) d = __builtin_fmaf(wk[t], v[t / 3][t % 3], d);
-            if (k == 0 || __builtin_fabsf(d) < __builtin_fabsf(best)) {
-                best = d;
-                bi = k;
+        for (int e = 0; e < C; ++e) pre[0][e] = pre[1][e];
+        fetch(pre[1], y + 3);
+        float best[C];
+        int bi[C];
+        auto kernel = [&](int k, const float* wk) {
+#pragma unroll
+            for (int e = 0; e < C; ++e) {
+                float d = wk[0] * v[0][e];
+#pragma unroll
+                for (int t = 1; t < 9; ++t) d = __builtin_fmaf(wk[t], v[t / 3][e + t % 3], d);
+                if (k == 0 || __builtin_fabsf(d) < __builtin_fabsf(best[e])) {
+                    best[e] = d;
+                    bi[e] = k;
+                }
+            }
+        };
+        if constexpr (KT > 0) {
+#pragma unroll
+            for (int k = 0; k < KT; ++k) kernel(k, wr + 9 * k);
+        } else {
+            for (int k = 0; k < A.K; ++k) {
+                float wk[9];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) wk[t] = wl[9 * k + t];
+                kernel(k, wk);
             }
         }
-        if (own) {
-            out[(int64_t)y * A.ld + x] = best;
-            if (sel) sel[(int64_t)y * A.ld + x] = (uint8_t)bi;
-        }
+        float* op = out + (int64_t)y * A.ld;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
+        for (int e = 0; e < C; ++e)
+            if (own[e]) {
+                op[xb + e] = best[e];
+                if (sel) sel[(int64_t)y * A.ld + xb + e] = (uint8_t)bi[e];
+            }
+#pragma unroll
+        for (int j = 0; j < C + 2; ++j) {
             v[0][j] = v[1][j];
             v[1][j] = v[2][j];
         }
@@ -123,30 +171,35 @@ struct LayerBwdArgs {
     const uint8_t* sel;
     const float* g;
     float* g_u;      // may be null
-    float* part;     // K*9 partial sums of gW per work item, or null
+    float* part;     // per work item and chunk: KC*9 partial sums of gW, or null
     int64_t n, h, w_, ld, ps;
     int32_t K, R, nstrip, nseg;
+    int32_t nchunk;  // ceil(K / KC) groups of kernels for gW
 };
 
 constexpr int kBwdHalo = 2;
 constexpr int kBwdStep = 64 - 2 * kBwdHalo;
+constexpr int kBwdChunk = 8;  // kernels whose gW one wave accumulates in registers
 
-// One wave per block; dynamic LDS: weights (K*9) then the per-lane
-// accumulators [K*9][64].
-__global__ __launch_bounds__(64) void k_layer_bwd(LayerBwdArgs A) {
-    extern __shared__ float lds[];
-    const int lane = threadIdx.x;
-    const int64_t per_plane = (int64_t)A.nseg * A.nstrip;
-    const int64_t total = A.n * per_plane;
-    const int64_t item = xcd_remap(blockIdx.x, gridDim.x);
-    if (item >= total) return;
-    const int K = A.K, KT = 9 * A.K;
-    float* wt = lds;
-    float* acc = lds + KT;
-    for (int i = lane; i < KT; i += 64) wt[i] = A.w[i];
-    if (A.part)
-        for (int i = 0; i < KT; ++i) acc[i * 64 + lane] = 0.0f;
+// Waves [0, items) of chunk c = wave / items accumulate gW for kernels
+// [c*KC, c*KC + KC); the waves of chunk 0 also write g_u.
+template <int KC>
+__global__ __launch_bounds__(256) void k_layer_bwd(LayerBwdArgs A) {
+    __shared__ float wt[9 * kLayerMaxK];
+    const int K = A.K;
+    for (int i = threadIdx.x; i < 9 * K; i += 256) wt[i] = A.w[i];
     __syncthreads();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t per_plane = (int64_t)A.nseg * A.nstrip;
+    const int64_t items = A.n * per_plane;
+    const int64_t wave = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
+    if (wave >= items * A.nchunk) return;
+    const int chunk = (int)(wave / items);
+    const int64_t item = wave - (int64_t)chunk * items;
+    const int kbase = chunk * KC;
+    const bool do_gu = chunk == 0 && A.g_u != nullptr;
+    const bool do_gw = A.part != nullptr;
 
     const int p = (int)(item / per_plane);
     const int rem = (int)(item - (int64_t)p * per_plane);
@@ -167,7 +220,13 @@ __global__ __launch_bounds__(64) void k_layer_bwd(LayerBwdArgs A) {
     const float* u = A.u + off;
     const float* g = A.g + off;
     const uint8_t* sel = A.sel + off;
-    float* gu = A.g_u ? A.g_u + off : nullptr;
+    float* gu = do_gu ? A.g_u + off : nullptr;
+
+    float acc[KC][9];
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[k][t] = 0.0f;
 
     // window rows rho-1, rho, rho+1: U with neighbours (replicate), g and m
     // with neighbours (g = 0 outside the image)
@@ -213,39 +272,38 @@ __global__ __launch_bounds__(64) void k_layer_bwd(LayerBwdArgs A) {
         const bool owned_row = rho >= y0 && rho < y1;
         const bool top = rho == -1 && y0 == 0;
         const bool bot = rho == H && y1 == H;
-        if (owned_row || top || bot) {
-            if (gu) {
-                // gU at (rho, x): neighbour (dy, dx) contributes w_{m}[(1-dy, 1-dx)] g
-                float a = 0.0f;
+        if (do_gu && (owned_row || top || bot)) {
+            // g_u at (rho, x): neighbour (dy, dx) contributes w_m[(1-dy, 1-dx)] g
+            float a = 0.0f;
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j)
-                        a = __builtin_fmaf(wt[mv[i][j] * 9 + (2 - i) * 3 + (2 - j)], gv[i][j], a);
-                if (edge) {
-                    // column ring: virtual column -1 onto 0, W onto W-1
-                    const float l = from_lower_lane(0.0f, a);
-                    const float r = from_upper_lane(0.0f, a);
-                    a += (isL ? l : 0.0f) + (isR ? r : 0.0f);
-                }
-                if (top) {
-                    topfold = a;
-                } else if (bot) {
-                    if (gu && own) gu[(int64_t)(H - 1) * A.ld + x] = a + pend;
-                } else {
-                    if (rho == 0) a += topfold;
-                    if (rho == H - 1) pend = a;
-                    else if (gu && own) gu[(int64_t)rho * A.ld + x] = a;
-                }
+                for (int j = 0; j < 3; ++j)
+                    a = __builtin_fmaf(wt[mv[i][j] * 9 + (2 - i) * 3 + (2 - j)], gv[i][j], a);
+            if (edge) {
+                // column ring: virtual column -1 onto 0, W onto W-1
+                const float l = from_lower_lane(0.0f, a);
+                const float r = from_upper_lane(0.0f, a);
+                a += (isL ? l : 0.0f) + (isR ? r : 0.0f);
             }
-            if (A.part && owned_row && own) {
-                const float gc = gv[1][1];
-                const int base = mv[1][1] * 9;
+            if (top) {
+                topfold = a;
+            } else if (bot) {
+                if (own) gu[(int64_t)(H - 1) * A.ld + x] = a + pend;
+            } else {
+                if (rho == 0) a += topfold;
+                if (rho == H - 1) pend = a;
+                else if (own) gu[(int64_t)rho * A.ld + x] = a;
+            }
+        }
+        if (do_gw && owned_row) {
+            const float gc = own ? gv[1][1] : 0.0f;
+            const int m = mv[1][1] - kbase;
 #pragma unroll
-                for (int t = 0; t < 9; ++t) {
-                    float* q = acc + (base + t) * 64 + lane;
-                    *q = __builtin_fmaf(gc, uv[t / 3][t % 3], *q);
-                }
+            for (int k = 0; k < KC; ++k) {
+                const float gk = (m == k) ? gc : 0.0f;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) acc[k][t] = __builtin_fmaf(gk, uv[t / 3][t % 3], acc[k][t]);
             }
         }
 #pragma unroll
@@ -255,58 +313,76 @@ __global__ __launch_bounds__(64) void k_layer_bwd(LayerBwdArgs A) {
             mv[0][j] = mv[1][j]; mv[1][j] = mv[2][j];
         }
     }
-    if (A.part) {
+    if (do_gw) {
         // fixed-order butterfly over the lanes of each (kernel, tap)
-        __syncthreads();
-        for (int e = 0; e < KT; ++e) {
-            float s = acc[e * 64 + lane];
+        float* dst = A.part + wave * (int64_t)(9 * KC);
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-            if (lane == 0) A.part[item * KT + e] = s;
-        }
+        for (int k = 0; k < KC; ++k)
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                float s = acc[k][t];
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+                if (lane == 0) dst[k * 9 + t] = s;
+            }
     }
 }
 
-// gW[e] = sum over work items of part[item][e], in item order.
+// gW[k][t] = sum over work items of the partial of chunk k / KC, in item order.
 __global__ __launch_bounds__(256) void k_layer_wreduce(const float* __restrict__ part,
-                                                       int64_t items, int KT,
+                                                       int64_t items, int KC, int K,
                                                        float* __restrict__ gw) {
-    const int e = blockIdx.x;
+    const int e = blockIdx.x;  // k * 9 + t
+    const int k = e / 9, t = e - 9 * (e / 9);
+    const int chunk = k / KC, kl = k - chunk * KC;
+    const float* base = part + (int64_t)chunk * items * (9 * KC) + kl * 9 + t;
     __shared__ float red[256];
     float s = 0.0f;
-    for (int64_t i = threadIdx.x; i < items; i += 256) s += part[i * KT + e];
+    for (int64_t i = threadIdx.x; i < items; i += 256) s += base[i * (9 * KC)];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) gw[e] = red[0];
+    if (threadIdx.x == 0 && k < K) gw[e] = red[0];
 }
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-static int layer_rows(int64_t n, int64_t h, int64_t strips) {
+static int layer_rows(int64_t n, int64_t h, int64_t strips, int64_t target) {
     const int64_t rows_total = n * h * strips;
     int R = 16;
-    while (R < 256 && rows_total / R > 8192) R *= 2;
+    while (R < 256 && rows_total / R > target) R *= 2;
     return R;
 }
 
+static int layer_chunk(int K) { return K < kBwdChunk ? K : kBwdChunk; }
+
 int layer_fwd_items(int64_t n, int64_t h, int64_t w, int* R, int* nstrip, int* nseg) {
     *nstrip = (int)((w + kFwdStep - 1) / kFwdStep);
-    *R = layer_rows(n, h, *nstrip);
+    *R = layer_rows(n, h, *nstrip, 8192);
     *nseg = seg_count((int)h, *R);
     return (int)std::min<int64_t>(n * (int64_t)(*nstrip) * (*nseg), 0x7fffffff);
 }
 
 int64_t layer_bwd_items(int64_t n, int64_t h, int64_t w, int* R, int* nstrip, int* nseg) {
     *nstrip = (int)((w + kBwdStep - 1) / kBwdStep);
-    *R = layer_rows(n, h, *nstrip);
+    *R = layer_rows(n, h, *nstrip, 4096);
     *nseg = seg_count((int)h, *R);
     return n * (int64_t)(*nstrip) * (*nseg);
 }
+
+int64_t layer_part_floats(int64_t n, int64_t h, int64_t w, int K) {
+    int R, ns, nsg;
+    const int64_t items = layer_bwd_items(n, h, w, &R, &ns, &nsg);
+    const int KC = layer_chunk(K);
+    return items * ((K + KC - 1) / KC) * 9 * KC;
+}
+
+using LayerFwdFn = void (*)(LayerFwdArgs);
+using LayerBwdFn = void (*)(LayerBwdArgs);
 
 hipError_t launch_layer_forward(const float* u, const float* w, int K, float* out, uint8_t* sel,
                                 int64_t n, int64_t h, int64_t wd, int64_t ld, int64_t ps,
@@ -328,8 +404,12 @@ hipError_t launch_layer_forward(const float* u, const float* w, int K, float* ou
     a.R = R;
     a.nstrip = ns;
     a.nseg = nsg;
+    static const LayerFwdFn tab[9] = {k_layer_fwd<0>, k_layer_fwd<1>, k_layer_fwd<2>,
+                                      k_layer_fwd<3>, k_layer_fwd<4>, k_layer_fwd<5>,
+                                      k_layer_fwd<6>, k_layer_fwd<7>, k_layer_fwd<8>};
+    const LayerFwdFn fn = tab[K <= 8 ? K : 0];
     const int64_t total = n * (int64_t)ns * nsg;
-    hipLaunchKernelGGL(k_layer_fwd, dim3((unsigned)((total + 3) / 4)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(fn, dim3((unsigned)((total + 3) / 4)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -355,12 +435,17 @@ hipError_t launch_layer_backward(const float* u, const float* w, int K, const ui
     a.R = R;
     a.nstrip = ns;
     a.nseg = nsg;
-    const size_t lds = (size_t)(9 * K) * sizeof(float) * (g_w ? 65 : 1);
-    hipLaunchKernelGGL(k_layer_bwd, dim3((unsigned)items), dim3(64), lds, st, a);
+    const int KC = layer_chunk(K);
+    a.nchunk = g_w ? (K + KC - 1) / KC : 1;
+    static const LayerBwdFn tab[9] = {nullptr, k_layer_bwd<1>, k_layer_bwd<2>, k_layer_bwd<3>,
+                                      k_layer_bwd<4>, k_layer_bwd<5>, k_layer_bwd<6>,
+                                      k_layer_bwd<7>, k_layer_bwd<8>};
+    const int64_t waves = items * a.nchunk;
+    hipLaunchKernelGGL(tab[KC], dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !g_w) return e;
     hipLaunchKernelGGL(k_layer_wreduce, dim3((unsigned)(9 * K)), dim3(256), 0, st, part, items,
-                       9 * K, g_w);
+                       KC, K, g_w);
     return hipGetLastError();
 }
 
