@@ -60,7 +60,8 @@ def kernel_sha():
 
 def read_traffic(tuning, side):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source and launch shape."""
+    was taken on the current kernel source and this launch shape (lines
+    "- hbm_bytes_per_launch[C,T,R]: N")."""
     path = os.path.join(ROOT, "profiles", f"stream_kernel_{side}_counters.md")
     if not os.path.exists(path):
         return None
@@ -70,13 +71,12 @@ def read_traffic(tuning, side):
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 kv[k.strip()] = v.strip().strip("`")
+    if kv.get("kernel_sha") != kernel_sha():
+        return None
+    key = f"hbm_bytes_per_launch[{tuning['cols']},{tuning['tsteps']},{tuning['seg_rows']}]"
     try:
-        if kv.get("kernel_sha") != kernel_sha():
-            return None
-        if kv.get("tuning") != f"{tuning['cols']},{tuning['tsteps']},{tuning['seg_rows']}":
-            return None
-        return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
+        return float(kv[key]) if key in kv else None
+    except ValueError:
         return None
 
 
@@ -272,13 +272,13 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side):
                 best = (gbs, t1)
         return best
 
-    gbs, t1 = t1_gbs(f, side, reps, [(2, 16), (2, 32), (4, 8), (4, 32)])
+    gbs, t1 = t1_gbs(f, side, reps, [(2, 14), (2, 16), (2, 28), (2, 32), (4, 8), (4, 23), (4, 32)])
     ex["step_T1_4096"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                           "gpx_per_s": round(gbs / BYTES_PER_PX_PASS, 2), "tuning": t1,
                           "note": "warm: the 192 MiB working set fits the 256 MB Infinity Cache"}
     # 8192^2 control, larger than the Infinity Cache
     g = torch.rand((1, 8192, 8192), device=f.device)
-    gbs, t1 = t1_gbs(g, 8192, 20, [(4, 4), (4, 8), (2, 4)])
+    gbs, t1 = t1_gbs(g, 8192, 20, [(4, 4), (4, 8), (2, 4), (2, 14), (4, 12)])
     ex["step_T1_8192"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                           "tuning": t1}
     del g

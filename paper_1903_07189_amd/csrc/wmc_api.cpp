@@ -160,16 +160,60 @@ void split_run(int len, int T, std::vector<int>& out) {
     }
 }
 
-// Output rows per work item: aim for ~32 waves per CU (memory latency hiding
-// for the single-sweep kernels), at least 8 rows (segment overlap).
-int default_rows(int64_t planes, int64_t h, int64_t w, int C, int T, int ncu) {
+// Output rows per work item.  A launch of the streaming kernel is a set of
+// equal work items (one wave each); when their number is just above a
+// multiple of the waves the device holds at once, the last round runs
+// nearly empty and the launch takes a whole extra round.  So R is chosen to
+// make the items fill k complete rounds: nseg = floor(k * slots / (planes *
+// strips)), R = ceil(h / nseg) -- the smallest k whose R is at least
+// max(8, 4T) rows (segment overlap costs T rows per sweep depth).  slots =
+// resident waves of this kernel variant (occupancy API) times the CUs.
+int64_t resident_waves(int dev, int C, int T, int mode) {
+    int per_cu = stream_single_blocks_per_cu(C, T, mode, false);
+    if (per_cu <= 0) per_cu = 1;
+    return (int64_t)num_cu(dev) * per_cu * 4;  // 4 waves per 256-thread block
+}
+
+int rows_for_rounds(int64_t planes, int64_t h, int64_t w, int C, int T, int64_t slots, int k) {
     const int64_t strips = strip_count((int)w, C, T);
-    const int64_t target = (int64_t)ncu * 32;
-    int64_t per_col = std::max<int64_t>(1, target / std::max<int64_t>(1, strips * planes));
-    int64_t R = (h + per_col - 1) / per_col;
-    R = std::max<int64_t>(R, std::max<int64_t>(8, 4 * (int64_t)T));
-    R = std::min<int64_t>(R, 256);
+    const int64_t nseg = std::max<int64_t>(1, (k * slots) / std::max<int64_t>(1, strips * planes));
+    const int64_t R = (h + nseg - 1) / nseg;
     return (int)std::max<int64_t>(1, std::min<int64_t>(R, h));
+}
+
+int default_rows(int64_t planes, int64_t h, int64_t w, int C, int T, int dev, int mode) {
+    const int64_t slots = resident_waves(dev, C, T, mode);
+    const int64_t rmin = std::min<int64_t>(h, std::max<int64_t>(8, 4 * (int64_t)T));
+    for (int k = 1; k <= 64; ++k) {
+        const int R = rows_for_rounds(planes, h, w, C, T, slots, k);
+        if (R < rmin) break;
+        if (R <= 512) return R;
+    }
+    return (int)rmin;
+}
+
+// Row counts worth timing for (C, T): the first three round-filling values
+// and two plain ones.
+std::vector<int> candidate_rows(int64_t planes, int64_t h, int64_t w, int C, int T, int dev,
+                                int mode) {
+    const int64_t slots = resident_waves(dev, C, T, mode);
+    std::vector<int> out;
+    auto add = [&](int R) {
+        if (R < 1 || R > 512) return;
+        if (std::find(out.begin(), out.end(), R) == out.end()) out.push_back(R);
+    };
+    const int64_t rmin = std::min<int64_t>(h, std::max<int64_t>(4, 2 * (int64_t)T));
+    for (int k = 1, got = 0; k <= 64 && got < 3; ++k) {
+        const int R = rows_for_rounds(planes, h, w, C, T, slots, k);
+        if (R < rmin) break;
+        if (R <= 512) {
+            add(R);
+            ++got;
+        }
+    }
+    add(16);
+    add(32);
+    return out;
 }
 
 // ---------------------------------------------------------------------------
@@ -587,8 +631,8 @@ int enqueue_l1(const wmc_shape& s, const float* src, const float* dsrc, const fl
 // ---------------------------------------------------------------------------
 // Times `run(C, T, R, stream)` (one launch of T sweeps) for every candidate and
 // returns the fastest per sweep.  Synchronises st.
-template <class Run>
-int tune_search(Run&& run, int64_t h_max, hipStream_t st, Tuned* best_out) {
+template <class Run, class Rows>
+int tune_search(Run&& run, Rows&& rows, hipStream_t st, Tuned* best_out) {
     hipEvent_t e0, e1;
     WMC_HIP(hipEventCreate(&e0), "hipEventCreate");
     WMC_HIP(hipEventCreate(&e1), "hipEventCreate");
@@ -597,9 +641,7 @@ int tune_search(Run&& run, int64_t h_max, hipStream_t st, Tuned* best_out) {
     int rc = WMC_OK;
     for (int C : {1, 2, 4})
         for (int T : {1, 2, 3, 4, 6, 8})
-            for (int R : {8, 16, 32, 64, 128}) {
-                if (R < 2 * T && R < h_max) continue;
-                if (R > 2 * h_max && R != 8) continue;
+            for (int R : rows(C, T)) {
                 // warm up once, then take the best of three
                 rc = run(C, T, R, st);
                 if (rc) goto done;
@@ -682,8 +724,10 @@ int get_tuning(const std::string& key, Tuned deflt, Search&& search, Tuned* t) {
 
 std::string single_tune_key(int dev, const wmc_shape& s, int mode) {
     std::ostringstream k;
-    k << arch_name(dev) << "|single|" << (mode == kModeData ? "data" : "flow") << "|h" << ilog2_ceil(s.h)
-      << "|w" << ilog2_ceil(s.w) << "|n" << ilog2_ceil(s.n);
+    // exact shape: the best row count depends on how the work items fill
+    // the device's wave slots
+    k << arch_name(dev) << "|single2|" << (mode == kModeData ? "data" : "flow") << "|h" << s.h
+      << "|w" << s.w << "|n" << s.n;
     return k.str();
 }
 
@@ -691,12 +735,13 @@ int tune_single(int dev, const wmc_shape& s, const float* src, const float* f, c
                 float dt, float* ws, hipStream_t st, Tuned* t) {
     const int mode = f ? kModeData : kModeFlow;
     const int C0 = std::min(2, vec_cols({src, f, ws}, s.ld, s.n > 1 ? s.ps : 0));
-    const Tuned deflt{C0, 4, default_rows(s.n, s.h, s.w, C0, 4, num_cu(dev))};
+    const Tuned deflt{C0, 3, default_rows(s.n, s.h, s.w, C0, 3, dev, mode)};
     auto search = [&](Tuned* out) {
         auto run = [&](int C, int T, int R, hipStream_t ss) {
             return enqueue_single(s, src, f, ws, lam, dt, C, T, R, ss);
         };
-        return tune_search(run, s.h, st, out);
+        auto rows = [&](int C, int T) { return candidate_rows(s.n, s.h, s.w, C, T, dev, mode); };
+        return tune_search(run, rows, st, out);
     };
     return get_tuning(single_tune_key(dev, s, mode), deflt, search, t);
 }
@@ -757,7 +802,19 @@ int tune_batch(int dev, const std::vector<BatchImg>& imgs, const float* lam, flo
             };
             return run_plan(key, dev, ss, false, prepare, enqueue);
         };
-        return tune_search(run, hmax, st, out);
+        // the persistent batched kernel pulls items from a counter: no round
+        // quantisation, plain row counts
+        auto rows = [&](int C, int T) {
+            (void)C;
+            std::vector<int> out;
+            for (int R : {8, 16, 32, 64, 128}) {
+                if (R < 2 * T && R < hmax) continue;
+                if (R > 2 * hmax && R != 8) continue;
+                out.push_back(R);
+            }
+            return out;
+        };
+        return tune_search(run, rows, st, out);
     };
     return get_tuning(batch_tune_key(dev, imgs, mode), deflt, search, t);
 }
@@ -823,7 +880,7 @@ int wmc_compute(const float* u, float* hw, wmc_shape s, void* stream) {
     rc = check_device(&dev);
     if (rc) return rc;
     const int C = std::min(2, vec_cols({u, hw}, s.ld, s.n > 1 ? s.ps : 0));
-    const int R = default_rows(s.n, s.h, s.w, C, 1, num_cu(dev));
+    const int R = default_rows(s.n, s.h, s.w, C, 1, dev, kModeCompute);
     ImageDesc d{};
     d.src0 = u;
     d.bufA = hw;
@@ -864,7 +921,7 @@ int wmc_step(const float* u, const float* f, float* u_out, const float* lam, flo
     if (rc) return rc;
     const int mode = f ? kModeData : kModeFlow;
     const int C = std::min(2, vec_cols({u, f, u_out}, s.ld, s.n > 1 ? s.ps : 0));
-    const int R = default_rows(s.n, s.h, s.w, C, 1, num_cu(dev));
+    const int R = default_rows(s.n, s.h, s.w, C, 1, dev, mode);
     ImageDesc d{};
     d.src0 = u;
     d.f = f;
@@ -1019,17 +1076,19 @@ int wmc_solve_l1(const float* f, const float* u0, const float* d0, float* u_out,
         rc = resolve_tuning(tune, Tuned{2, 3, 16}, &t, &graph);
     } else {
         const Tuned deflt{std::min(2, vec_cols({src0, f, u_out}, s.ld, s.n > 1 ? s.ps : 0)), 3,
-                          default_rows(s.n, s.h, s.w, 2, 3, num_cu(dev))};
+                          default_rows(s.n, s.h, s.w, 2, 3, dev, kModeL1)};
         std::ostringstream k;
-        k << arch_name(dev) << "|single|l1|h" << ilog2_ceil(s.h) << "|w" << ilog2_ceil(s.w) << "|n"
-          << ilog2_ceil(s.n);
+        k << arch_name(dev) << "|single2|l1|h" << s.h << "|w" << s.w << "|n" << s.n;
         auto search = [&](Tuned* out) {
             float* scratchU = iters >= 2 ? wsU : u_out;
             float* scratchD = iters >= 2 ? wsD : d_out;
             auto run = [&](int C, int T, int R, hipStream_t ss) {
                 return enqueue_l1(s, src0, d0, f, scratchU, scratchD, lam, alpha, dt, C, T, R, ss);
             };
-            return tune_search(run, s.h, st, out);
+            auto rows = [&](int C, int T) {
+                return candidate_rows(s.n, s.h, s.w, C, T, dev, kModeL1);
+            };
+            return tune_search(run, rows, st, out);
         };
         Tuned auto_t{};
         rc = get_tuning(k.str(), deflt, search, &auto_t);
@@ -1284,7 +1343,7 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     const bool data = f != nullptr;
     // recompute launches: plain single sweeps, paired columns when aligned
     const int C1 = std::min(2, vec_cols({ckpt, states, f, u0}, s.ld, s.n > 1 ? s.ps : 0));
-    const int R1 = default_rows(s.n, s.h, s.w, C1, 1, num_cu(dev));
+    const int R1 = default_rows(s.n, s.h, s.w, C1, 1, dev, data ? kModeData : kModeFlow);
     // adjoint launches (WMC_ADJ_COLS=2|4 selects wider lanes)
     const char* env_cols = std::getenv("WMC_ADJ_COLS");
     int CA = 1;

@@ -72,6 +72,7 @@ hipError_t launch_stream_batched(int C, int T, int mode, const ImageDesc* dtable
                                  int64_t total_items, const LaunchArgs& a, uint32_t* counter,
                                  int grid_blocks, hipStream_t st);
 int stream_blocks_per_cu(int C, int T, int mode);
+int stream_single_blocks_per_cu(int C, int T, int mode, bool argmin);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 hipError_t launch_copy_planes(const float* src, float* dst, int64_t n, int64_t h, int64_t w,

@@ -501,6 +501,16 @@ hipError_t launch_stream_single(int C, int T, int mode, bool argmin, const Image
     return hipGetLastError();
 }
 
+int stream_single_blocks_per_cu(int C, int T, int mode, bool argmin) {
+    SingleFn fn = single_table(C, T, mode, argmin);
+    if (!fn) return 0;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn), kBlock,
+                                                     0) != hipSuccess)
+        return 0;
+    return nb;
+}
+
 int stream_blocks_per_cu(int C, int T, int mode) {
     BatchedFn fn = batched_table(C, T, mode);
     if (!fn) return 0;

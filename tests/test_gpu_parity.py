@@ -316,3 +316,34 @@ def test_invariants_on_gpu(wmc):
     assert len(moved) == 4
     for yy, xx in moved:
         assert r1[yy, xx] == pytest.approx(1 - (1 / 3) * 2 / 6, abs=1e-6)
+
+
+@pytest.mark.parametrize("kind", ["random", "integers", "dyadic", "tiny_a", "flat_patches"])
+def test_selection_map_variant_is_bitwise_equal(wmc, kind):
+    """The selection-map variant (select with index) and the plain kernels
+    (select value only) must produce bitwise the same update on inputs rich
+    in exact ties, absorbed A and signed zeros (data and flow mode)."""
+    rng = np.random.default_rng(["random", "integers", "dyadic", "tiny_a", "flat_patches"].index(kind))
+    H, W = 97, 203
+    if kind == "random":
+        U = rng.uniform(0, 1, size=(2, H, W))
+    elif kind == "integers":
+        U = rng.integers(0, 4, size=(2, H, W)).astype(np.float64)
+    elif kind == "dyadic":
+        U = rng.integers(0, 64, size=(2, H, W)) / 16.0
+    elif kind == "tiny_a":
+        # a smooth quadratic bowl plus 1e-9 jitter: A ~ 0 against large odd parts
+        yy, xx = np.mgrid[0:H, 0:W]
+        U = np.stack([0.3 * xx + 0.2 * yy + 1e-9 * rng.standard_normal((H, W))] * 2)
+    else:
+        U = np.repeat(np.repeat(rng.uniform(0, 1, size=(2, H // 8 + 1, W // 8 + 1)), 8, 1), 8, 2)
+        U = U[:, :H, :W]
+    u = to_gpu(U)
+    f = to_gpu(rng.uniform(0, 1, size=(2, H, W)))
+    lam = torch.tensor([1.0, 3.0], device="cuda:0")
+    for ff in (f, None):
+        a = wmc.step(u, ff, lam, dt=0.3)
+        b, _ = wmc.step(u, ff, lam, dt=0.3, return_argmin=True)
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+    h = wmc.compute(u)
+    assert torch.isfinite(h).all()
