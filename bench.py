@@ -113,7 +113,45 @@ def cpu_baseline(side: int, sample_iters: int):
     out["samples"] = {"c1_256_50_iters_s": round(t_c1, 3),
                       "c1_gpx_iter_s": round(256 * 256 * 50 / t_c1 / 1e9, 6),
                       "c4_one_image_fwd_adjoint_s": round(t_c4, 3)}
+    out["aggregate"] = aggregate_oracle()
     return out
+
+
+def _oracle_job(args):
+    b, h, w, sig, iters = args
+    import time as _t
+    import oracle
+    import wmc_synth
+    noisy, _ = wmc_synth.c3_image(b, h, w, sig)
+    t0 = _t.perf_counter()
+    oracle.solve(noisy[0], lam=1.0, iters=iters)
+    return h * w * iters, _t.perf_counter() - t0
+
+
+def aggregate_oracle(max_procs: int = 16, iters: int = 2):
+    """Host throughput with one oracle process per core on the uneven batch
+    (first channel of the first `procs` images, `iters` iterations each):
+    the sum of the processes' own rates (all cores busy).  Child processes
+    are started fresh (spawn) and never touch the GPU."""
+    import multiprocessing as mp
+    import wmc_synth
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        cores = os.cpu_count() or 1
+    procs = max(1, min(max_procs, cores))
+    sizes = wmc_synth.c3_sizes()[:procs]
+    jobs = [(b, h, w, s, iters) for b, (h, w, s) in enumerate(sizes)]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_oracle_job, jobs)
+    wall = time.perf_counter() - t0
+    rate = sum(r[0] / r[1] for r in res)
+    slowest = max(r[1] for r in res)
+    return {"value": round(rate / 1e9, 6), "unit": "Gpixel-iter/s", "cores": procs,
+            "sample": f"{procs} processes, one C3 image channel each, {iters} iterations "
+                      f"(slowest {slowest:.1f} s, wall incl. start-up {wall:.1f} s)"}
 
 
 def train_step_fn(torch, wmc, wmc_synth, dev):
@@ -256,6 +294,14 @@ def main():
 
 def extras(torch, wmc, wmc_synth, f, lam, stream, side):
     ex = {}
+    # device copy ceiling: 1 GiB read + 1 GiB written
+    a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=f.device).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = timed(lambda: b.copy_(a), 5, stream, torch) / 5
+    ex["copy_ceiling"] = {"gbs": round(2 * a.numel() * 4 / (ms * 1e-3) / 1e9, 1),
+                          "note": "torch copy of 1 GiB (read + write), the practical HBM ceiling"}
+    del a, b
     # plain single-update kernel (one launch per iteration, graph-replayed); the
     # launch shape is picked from a few candidates, best reported
     reps = 50
@@ -354,7 +400,18 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side):
             p()
     run_plain()
     ms_p = timed(run_plain, 2, stream, torch) / 2
+    # per image, graph-replayed fused solves (the library's best single-image path)
+    gplans = [wmc.SolvePlan(x, lams[i:i + 1].expand(x.shape[0]).contiguous(), 100)
+              for i, x in enumerate(imgs)]
+
+    def run_graphed():
+        for p in gplans:
+            p()
+    run_graphed()
+    ms_g = timed(run_graphed, 2, stream, torch) / 2
     ex["batched_c3"] = {"channel_px": px, "iters": 100,
+                        "per_image_graphed_gpx_iter_s": round(px * 100 / (ms_g * 1e-3) / 1e9, 2),
+                        "speedup_vs_graphed": round(ms_g / ms_b, 2),
                         "batched_gpx_iter_s": round(px * 100 / (ms_b * 1e-3) / 1e9, 2),
                         "per_image_plain_gpx_iter_s": round(px * 100 / (ms_p * 1e-3) / 1e9, 2),
                         "speedup": round(ms_p / ms_b, 2), "ms_batched": round(ms_b, 3),

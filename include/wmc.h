@@ -253,6 +253,24 @@ int wmc_fd_compute(const float* u, float* hw, float eps, wmc_shape s, void* stre
 int wmc_fd_flow(const float* u0, float* u_out, int iters, float dt, float eps, void* ws,
                 size_t ws_bytes, wmc_shape s, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * wmc_workspace_bytes -- one query for every workspace size:
+ *   WMC_OP_SOLVE, WMC_OP_FD_FLOW   wmc_solve_workspace(s)
+ *   WMC_OP_SOLVE_L1                wmc_l1_workspace(s)
+ *   WMC_OP_BACKWARD                wmc_backward_workspace(s, iters, ckpt_every)
+ *   WMC_OP_LAYER_BACKWARD          wmc_layer_workspace(s, K = iters)
+ * 0 for an invalid shape or op.  (The batched solver's size depends on its
+ * image list: wmc_batched_workspace.)
+ * ------------------------------------------------------------------------- */
+enum {
+    WMC_OP_SOLVE = 0,
+    WMC_OP_SOLVE_L1 = 1,
+    WMC_OP_BACKWARD = 2,
+    WMC_OP_FD_FLOW = 3,
+    WMC_OP_LAYER_BACKWARD = 4
+};
+size_t wmc_workspace_bytes(int op, wmc_shape s, int iters, int ckpt_every);
+
 /* Checks on the current device that the wavefront lane shifts the kernels
  * rely on move data as expected; returns WMC_OK or WMC_EHIP/WMC_EUNSUPPORTED.
  * Synchronises the default stream. */

@@ -1470,6 +1470,17 @@ int wmc_layer_backward(const float* u, const float* w, int K, const uint8_t* sel
     return e == hipSuccess ? WMC_OK : hip_fail(e, "wmc_layer_backward launch");
 }
 
+size_t wmc_workspace_bytes(int op, wmc_shape s, int iters, int ckpt_every) {
+    switch (op) {
+        case WMC_OP_SOLVE:
+        case WMC_OP_FD_FLOW: return wmc_solve_workspace(s);
+        case WMC_OP_SOLVE_L1: return wmc_l1_workspace(s);
+        case WMC_OP_BACKWARD: return wmc_backward_workspace(s, iters, ckpt_every);
+        case WMC_OP_LAYER_BACKWARD: return wmc_layer_workspace(s, iters);
+        default: return 0;
+    }
+}
+
 int wmc_fd_compute(const float* u, float* hw, float eps, wmc_shape s, void* stream) {
     g_err.clear();
     int rc = check_shape(s);

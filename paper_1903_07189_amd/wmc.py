@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwmc.so")
 
 WMC_OK, WMC_EINVAL, WMC_EHIP, WMC_ENOMEM, WMC_EUNSUPPORTED = 0, -1, -2, -3, -4
+WMC_OP_SOLVE, WMC_OP_SOLVE_L1, WMC_OP_BACKWARD, WMC_OP_FD_FLOW, WMC_OP_LAYER_BACKWARD = 0, 1, 2, 3, 4
 
 
 class WMCError(RuntimeError):
@@ -49,7 +50,7 @@ _lib = None
 EXPORTS = ["wmc_compute", "wmc_step", "wmc_solve_workspace", "wmc_set_stride",
            "wmc_num_checkpoints", "wmc_solve", "wmc_solve_tuning", "wmc_l1_workspace",
            "wmc_solve_l1", "wmc_fd_compute", "wmc_fd_flow", "wmc_layer_workspace",
-           "wmc_layer_forward", "wmc_layer_backward",
+           "wmc_layer_forward", "wmc_layer_backward", "wmc_workspace_bytes",
            "wmc_batched_workspace", "wmc_solve_batched", "wmc_autotune", "wmc_backward_workspace",
            "wmc_backward", "wmc_selftest", "wmc_last_error", "wmc_release"]
 
@@ -79,6 +80,8 @@ def lib():
     L.wmc_solve_l1.argtypes = [P, P, P, P, P, P, F, I, F, ctypes.POINTER(Tuning), P, SZ, Shape, P]
     L.wmc_fd_compute.argtypes = [P, P, F, Shape, P]
     L.wmc_fd_flow.argtypes = [P, P, I, F, F, P, SZ, Shape, P]
+    L.wmc_workspace_bytes.argtypes = [I, Shape, I, I]
+    L.wmc_workspace_bytes.restype = SZ
     L.wmc_layer_workspace.argtypes = [Shape, I]
     L.wmc_layer_workspace.restype = SZ
     L.wmc_layer_forward.argtypes = [P, P, I, P, P, Shape, P]

@@ -54,6 +54,19 @@ def test_workspace_queries(wmc):
     assert L.wmc_backward_workspace(S(1, 32, 32, 32, 1024), 20, 0) == 0
 
 
+def test_workspace_bytes_dispatch(wmc):
+    L = wmc.lib()
+    S = wmc.Shape(2, 100, 130, 130, 100 * 130)
+    assert L.wmc_workspace_bytes(wmc.WMC_OP_SOLVE, S, 0, 0) == L.wmc_solve_workspace(S)
+    assert L.wmc_workspace_bytes(wmc.WMC_OP_FD_FLOW, S, 0, 0) == L.wmc_solve_workspace(S)
+    assert L.wmc_workspace_bytes(wmc.WMC_OP_SOLVE_L1, S, 0, 0) == L.wmc_l1_workspace(S)
+    assert L.wmc_workspace_bytes(wmc.WMC_OP_BACKWARD, S, 20, 5) == L.wmc_backward_workspace(S, 20, 5)
+    assert L.wmc_workspace_bytes(wmc.WMC_OP_LAYER_BACKWARD, S, 8, 0) == L.wmc_layer_workspace(S, 8)
+    assert L.wmc_layer_workspace(S, 8) > 0 and L.wmc_layer_workspace(S, 17) == 0
+    assert L.wmc_workspace_bytes(99, S, 0, 0) == 0
+    assert L.wmc_workspace_bytes(wmc.WMC_OP_SOLVE, wmc.Shape(0, 1, 1, 1, 1), 0, 0) == 0
+
+
 P = ctypes.c_void_p
 
 
@@ -155,3 +168,24 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(W, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         W.lib()
+
+
+def test_layer_and_fd_validation(wmc):
+    L = wmc.lib()
+    S = wmc.Shape(1, 8, 8, 8, 64)
+    for K in (0, 17):
+        assert L.wmc_layer_forward(P(4096), P(8192), K, P(1 << 20), None, S, None) == wmc.WMC_EINVAL
+        assert "K must be" in L.wmc_last_error().decode()
+    assert L.wmc_layer_forward(None, P(8192), 8, P(1 << 20), None, S, None) == wmc.WMC_EINVAL
+    # output aliasing the input
+    assert L.wmc_layer_forward(P(4096), P(1 << 22), 8, P(4096 + 8), None, S, None) == wmc.WMC_EINVAL
+    # weight gradient without enough workspace
+    assert L.wmc_layer_backward(P(4096), P(1 << 22), 8, P(1 << 23), P(1 << 24), None, P(1 << 25),
+                                P(1 << 26), 4, S, None) == wmc.WMC_ENOMEM
+    # nothing requested: a no-op
+    assert L.wmc_layer_backward(P(4096), P(1 << 22), 8, P(1 << 23), P(1 << 24), None, None,
+                                None, 0, S, None) == wmc.WMC_OK
+    # finite-difference comparator
+    assert L.wmc_fd_compute(P(4096), P(1 << 20), -1.0, S, None) == wmc.WMC_EINVAL
+    assert L.wmc_fd_flow(P(4096), P(1 << 20), -1, 0.1, 1e-12, None, 0, S, None) == wmc.WMC_EINVAL
+    assert L.wmc_fd_flow(P(4096), P(1 << 20), 5, 0.1, 1e-12, P(1 << 21), 8, S, None) == wmc.WMC_ENOMEM
