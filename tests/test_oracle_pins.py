@@ -883,3 +883,10 @@ def test_layer_backward_dot_product_and_weight_fd():
                 assert np.array_equal(mp, m) and np.array_equal(mm, m)
                 fd = (np.sum(g * op) - np.sum(g * om)) / (2 * eps)
                 assert abs(fd - gW[k, r, c]) <= 1e-6 * max(1.0, abs(gW[k, r, c]))
+
+
+def test_network_module_kernel_table_matches_the_oracle():
+    """The package's initialiser table (nn.py) and the oracle's table are
+    transcribed separately from Sec. 4.2; they must agree entry for entry."""
+    from paper_1903_07189_amd.nn import PRINTED_KERNELS_X12
+    assert np.array_equal(np.array(PRINTED_KERNELS_X12), oracle.kernel_table())
