@@ -86,9 +86,10 @@ def cpu_baseline(side: int, sample_iters: int):
     import oracle
     import wmc_synth
     try:
-        os.sched_setaffinity(0, {sorted(os.sched_getaffinity(0))[0]})
+        cpus = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {sorted(cpus)[0]})
     except (AttributeError, OSError):
-        pass
+        cpus = None
     noisy, _ = wmc_synth.c2(side=side)
     f = noisy[0].astype(np.float64)
     t0 = time.perf_counter()
@@ -113,6 +114,8 @@ def cpu_baseline(side: int, sample_iters: int):
     out["samples"] = {"c1_256_50_iters_s": round(t_c1, 3),
                       "c1_gpx_iter_s": round(256 * 256 * 50 / t_c1 / 1e9, 6),
                       "c4_one_image_fwd_adjoint_s": round(t_c4, 3)}
+    if cpus:
+        os.sched_setaffinity(0, cpus)  # the aggregate sample uses every core
     out["aggregate"] = aggregate_oracle()
     return out
 
@@ -154,10 +157,11 @@ def aggregate_oracle(max_procs: int = 16, iters: int = 2):
                       f"(slowest {slowest:.1f} s, wall incl. start-up {wall:.1f} s)"}
 
 
-def train_step_fn(torch, wmc, wmc_synth, dev):
+def train_step_fn(torch, wmc, wmc_synth, dev, ckpt_every=None):
     """One optimisation step's worth of work on the 16 x 512 x 512, K = 20
-    workload: the fused forward with checkpoints every 5 steps, the MSE loss
-    against the clean images, and backward through the adjoint to f and lam."""
+    workload: the fused forward with checkpoints (default period: every state
+    while they fit the budget, else ceil(sqrt(K))), the MSE loss against the
+    clean images, and backward through the adjoint to f and lam."""
     noisy, clean = wmc_synth.c4()
     x = torch.from_numpy(noisy[:, 0]).to(dev)
     y = torch.from_numpy(clean[:, 0]).to(dev)
@@ -165,7 +169,7 @@ def train_step_fn(torch, wmc, wmc_synth, dev):
     xg = x.clone().requires_grad_(True)
 
     def step():
-        u = wmc.WMCSolve.apply(xg, lam16, 20)
+        u = wmc.WMCSolve.apply(xg, lam16, 20, 0.0, ckpt_every)
         loss = torch.mean((u - y) ** 2)
         loss.backward()
     return step, x
@@ -356,17 +360,20 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side):
     del us, fs, outs
     # differentiable solve (16 x 512 x 512, K = 20, checkpoint every 5): one
     # training step = fused forward with checkpoints + hand-written adjoint
-    train_step, x = train_step_fn(torch, wmc, wmc_synth, f.device)
-    train_step()
-    ms_t = timed(train_step, 5, stream, torch) / 5
-    lam16 = torch.ones(16, device=f.device)
-    ms_f = timed(lambda: wmc.solve(x, lam16, 20, ckpt_every=5), 5, stream, torch) / 5
     pxs = 16 * 512 * 512 * 20
-    ex["c4_train_step"] = {"ms_forward_backward": round(ms_t, 3), "ms_forward_ckpt": round(ms_f, 3),
-                           "forward_gpx_iter_s": round(pxs / (ms_f * 1e-3) / 1e9, 1),
-                           "backward_gpx_step_s": round(pxs / ((ms_t - ms_f) * 1e-3) / 1e9, 1),
-                           "note": "backward = segment recompute + adjoint steps + lam reduction"}
-    del x
+    lam16 = torch.ones(16, device=f.device)
+    for name, c in (("c4_train_step", 5), ("c4_train_step_all_states", 1)):
+        train_step, x = train_step_fn(torch, wmc, wmc_synth, f.device, c)
+        train_step()
+        ms_t = timed(train_step, 5, stream, torch) / 5
+        ms_f = timed(lambda: wmc.solve(x, lam16, 20, ckpt_every=c), 5, stream, torch) / 5
+        ex[name] = {"ckpt_every": c, "ms_forward_backward": round(ms_t, 3),
+                    "ms_forward_ckpt": round(ms_f, 3),
+                    "forward_gpx_iter_s": round(pxs / (ms_f * 1e-3) / 1e9, 1),
+                    "backward_gpx_step_s": round(pxs / ((ms_t - ms_f) * 1e-3) / 1e9, 1),
+                    "note": "backward = segment recompute (none at period 1) + adjoint steps "
+                            "+ lam reduction"}
+        del x
     # learnable half-window layer, 8 kernels, on the 16 x 512^2 batch
     xw = torch.from_numpy(wmc_synth.c4()[0][:, 0]).to(f.device)
     kw = wmc.nn.printed_kernels(device=f.device)

@@ -481,7 +481,10 @@ class WMCSolve(torch.autograd.Function):
     """U^K = solve(f, lam, K) as a differentiable layer: forward runs the fused
     solver storing a checkpoint every ckpt_every steps (default ceil(sqrt(K))),
     backward runs the hand-written adjoint, recomputing each segment from its
-    checkpoint.  Gradients flow to f (N, H, W) and to lam (N,)."""
+    checkpoint.  Gradients flow to f (N, H, W) and to lam (N,).  (Keeping every
+    state, ckpt_every = 1, removes the recomputation but not the time: the
+    adjoint then reads states that are no longer in the Infinity Cache, and
+    the forward cannot fuse sweeps.)"""
 
     @staticmethod
     def forward(ctx, f, lam, K: int, dt: float = 0.0, ckpt_every: int | None = None, tuning=None):

@@ -126,3 +126,28 @@ def test_autograd_function(wmc):
     gu, gw = wmc.layer_backward(U, w, sel, g)
     assert torch.equal(out.detach(), ref_out)
     assert torch.equal(u.grad, gu) and torch.equal(wp.grad, gw)
+
+
+def test_layer_at_the_benchmark_size(wmc):
+    """16 x 512 x 512, K = 8 printed-plus-learned-like kernels (the size the
+    benchmark times): every output and the gradients against the oracle."""
+    noisy, _ = wmc_synth.c4()
+    U = noisy[:, 0]
+    rng = np.random.default_rng(12)
+    from paper_1903_07189_amd.nn import PRINTED_KERNELS_X12
+    w = (np.array(PRINTED_KERNELS_X12, dtype=np.float32) / 12.0
+         + 0.05 * rng.standard_normal((8, 3, 3))).astype(np.float32)
+    Ug, wg = to_gpu(U), to_gpu(w)
+    out, sel = wmc.layer_forward(Ug, wg)
+    g = rng.standard_normal(U.shape).astype(np.float32)
+    g_u, g_w = wmc.layer_backward(Ug, wg, sel, to_gpu(g))
+    out, sel, g_u = out.cpu().numpy(), sel.cpu().numpy(), g_u.cpu().numpy()
+    gw_ref = np.zeros((8, 3, 3))
+    agree = []
+    for p in range(U.shape[0]):
+        agree.append(check_forward(U[p], w, out[p], sel[p]))
+        gu_ref, gw_p = oracle.layer_backward(U[p], w, sel[p].astype(np.int8), g[p])
+        gw_ref += gw_p
+        assert np.linalg.norm(g_u[p] - gu_ref) <= 1e-5 * np.linalg.norm(gu_ref)
+    assert min(agree) > 0.999
+    assert np.linalg.norm(g_w.cpu().numpy() - gw_ref) <= 2e-5 * np.linalg.norm(gw_ref)
