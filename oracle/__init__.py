@@ -23,6 +23,9 @@ Curvature", arXiv 1903.07189):
 * :func:`layer_forward` / :func:`layer_backward` -- the learnable half-window
   layer of Sec. 4.3 (K learned 3x3 kernels, minimum-magnitude activation) and
   its derivative with the selection held fixed.
+* :func:`kernels3` / :func:`compute3` / :func:`solve3` -- the 3-D extension
+  mentioned in the conclusion, built like Sec. 4.1 builds the 2-D kernels
+  (18 half windows of the tensor-product Laplacian, see O13).
 * :func:`listing` -- the Appendix A function's semantics (zero padding, true
   convolution, its candidate order).
 * :func:`step_adjoint` / :func:`solve_adjoint` -- derivative of the update map
@@ -86,6 +89,9 @@ def _load():
         lib.wmco_fd_flow.argtypes = [P, I64, I64, D, D, I, P]
         lib.wmco_layer_forward.argtypes = [P, I64, I64, I, P, P, P]
         lib.wmco_layer_backward.argtypes = [P, I64, I64, I, P, P, P, P, P]
+        lib.wmco3_kernels.argtypes = [P]
+        lib.wmco3_compute.argtypes = [P, I64, I64, I64, P, P]
+        lib.wmco3_solve.argtypes = [P, P, I64, I64, I64, D, D, I, P]
         _lib = lib
     return _lib
 
@@ -384,3 +390,41 @@ def layer_backward(U, w, m, g):
     gW = np.empty((K, 3, 3))
     _load().wmco_layer_backward(_p(U), H, W, K, _p(w), _p(m), _p(g), _p(gU), _p(gW))
     return gU, gW
+
+
+def _d3(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != 3:
+        raise ValueError("3-D functions take one (D, H, W) volume")
+    return a
+
+
+def kernels3() -> np.ndarray:
+    """The 18 half-window kernels of the 3-D extension, x56, shape (18, 3, 3, 3)
+    indexed [i][dz+1][dy+1][dx+1] (O13)."""
+    out = np.empty(18 * 27, dtype=np.int32)
+    _load().wmco3_kernels(out.ctypes.data_as(ctypes.c_void_p))
+    return out.reshape(18, 3, 3, 3)
+
+
+def compute3(U, return_argmin: bool = False):
+    U = _d3(U)
+    D, H, W = U.shape
+    Hd = np.empty_like(U)
+    m = np.empty(U.shape, dtype=np.int8)
+    _load().wmco3_compute(_p(U), D, H, W, _p(Hd), _p(m))
+    return (Hd, m) if return_argmin else Hd
+
+
+def solve3(f=None, lam: float = 1.0, iters: int = 1, delta: float | None = None, u0=None):
+    if f is None and u0 is None:
+        raise ValueError("flow mode needs u0")
+    f = None if f is None else _d3(f)
+    u0 = None if u0 is None else _d3(u0)
+    ref = f if f is not None else u0
+    D, H, W = ref.shape
+    if delta is None:
+        delta = default_delta(lam, f is None)
+    out = np.empty_like(ref)
+    _load().wmco3_solve(_p(f), _p(u0), D, H, W, float(lam), float(delta), int(iters), _p(out))
+    return out

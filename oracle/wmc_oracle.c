@@ -37,7 +37,10 @@
  *   O12 the learnable half-window layer of Sec. 4.3: K learned 3x3 kernels
  *       (eq. (conv) with the h_i replaced by learned weights) followed by the
  *       minimum-magnitude activation of eq. (act), and its derivative with
- *       respect to the input and the kernel weights.
+ *       respect to the input and the kernel weights;
+ *   O13 the extension to 3-D volumes that the conclusion mentions (Sec. 6);
+ *       the paper gives no kernels, so they are built the way Sec. 4.1 builds
+ *       the 2-D ones (see O13 below).
  *
  * Images are row-major H x W arrays of doubles, x = column, y = row
  * (downwards).  Functions never allocate more than O(H W) scratch.
@@ -461,4 +464,103 @@ void wmco_layer_backward(const double* U, int64_t H, int64_t W, int K, const dou
                     gW[(k * 3 + r) * 3 + c] += gv * U[zy * W + zx];
                 }
         }
+}
+
+/* O13: half-window WMC of a 3-D volume U (D x H x W, z slowest).
+ *
+ * Sec. 4.1 builds the 2-D operator from the isotropic Laplacian k4 and a
+ * Neumann reflection of k4 across each cut line through the centre; k4 is
+ * (s x s - 16 delta)/12 with s = [1 2 1].  The 3-D construction here follows
+ * the same two steps (the paper does not specify one):
+ *   K = (s x s x s - 64 delta)/56  (off-centre weights 1 at corners, 2 on
+ *       edges, 4 on faces of the 3x3x3 window, centre -1 after / 56);
+ *   the cut planes are the 9 mirror planes of the cube (normals e_x, e_y,
+ *   e_z and the 6 face diagonals e_x +- e_y, e_x +- e_z, e_y +- e_z), so the
+ *   reflection maps the window onto itself as in 2-D; for each plane and
+ *   side the half window keeps the weights on the kept side and on the
+ *   plane and adds the reflected weights of the other side.
+ * The 18 responses S_i (x56 domain) are evaluated in the difference form
+ * sum_{o != 0} w_i[o] (Ubar(x + o) - U(x)) with the replicate border;
+ * m = first index with the least |S_i| in the order plane 0..8, side
+ * "-" (keep n.o <= 0) before side "+"; H = S_m / 56. */
+static const int N3[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0},
+                             {1, 0, 1}, {1, 0, -1}, {0, 1, 1}, {0, 1, -1}};
+
+static int s121(int o) { return o == 0 ? 2 : 1; }
+
+/* w[i][dz+1][dy+1][dx+1] for i = 2*plane + side (side 0: keep n.o <= 0). */
+void wmco3_kernels(int* w) {
+    for (int j = 0; j < 9; ++j)
+        for (int side = 0; side < 2; ++side) {
+            int* k = w + (2 * j + side) * 27;
+            for (int t = 0; t < 27; ++t) k[t] = 0;
+            const int sg = side == 0 ? 1 : -1;  /* kept side: sg * n.o <= 0 */
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (!dx && !dy && !dz) continue;
+                        const int c = s121(dx) * s121(dy) * s121(dz);
+                        const int d = sg * (N3[j][0] * dx + N3[j][1] * dy + N3[j][2] * dz);
+                        const int nn = N3[j][0] * N3[j][0] + N3[j][1] * N3[j][1] + N3[j][2] * N3[j][2];
+                        int tx = dx, ty = dy, tz = dz;
+                        if (d > 0) { /* reflect across the plane onto the kept side */
+                            const int dot = N3[j][0] * dx + N3[j][1] * dy + N3[j][2] * dz;
+                            tx = dx - 2 * dot * N3[j][0] / nn;
+                            ty = dy - 2 * dot * N3[j][1] / nn;
+                            tz = dz - 2 * dot * N3[j][2] / nn;
+                        }
+                        k[((tz + 1) * 3 + (ty + 1)) * 3 + (tx + 1)] += c;
+                    }
+            k[13] = -56;
+        }
+}
+
+static double ubar3(const double* U, int64_t D, int64_t H, int64_t W, int64_t z, int64_t y,
+                    int64_t x) {
+    return U[(clampi(z, 0, D - 1) * H + clampi(y, 0, H - 1)) * W + clampi(x, 0, W - 1)];
+}
+
+void wmco3_compute(const double* U, int64_t D, int64_t H, int64_t W, double* Hd, int8_t* m_out) {
+    int w[18 * 27];
+    wmco3_kernels(w);
+    for (int64_t z = 0; z < D; ++z)
+        for (int64_t y = 0; y < H; ++y)
+            for (int64_t x = 0; x < W; ++x) {
+                const double c = U[(z * H + y) * W + x];
+                double best = 0.0;
+                int bi = 0;
+                for (int i = 0; i < 18; ++i) {
+                    double S = 0.0;
+                    for (int dz = -1; dz <= 1; ++dz)
+                        for (int dy = -1; dy <= 1; ++dy)
+                            for (int dx = -1; dx <= 1; ++dx) {
+                                const int t = ((dz + 1) * 3 + (dy + 1)) * 3 + (dx + 1);
+                                if (t == 13 || !w[i * 27 + t]) continue;
+                                S += w[i * 27 + t] * (ubar3(U, D, H, W, z + dz, y + dy, x + dx) - c);
+                            }
+                    if (i == 0 || fabs(S) < fabs(best)) {
+                        best = S;
+                        bi = i;
+                    }
+                }
+                Hd[(z * H + y) * W + x] = best / 56.0;
+                if (m_out) m_out[(z * H + y) * W + x] = (int8_t)bi;
+            }
+}
+
+/* O13: Jacobi steps of the data or flow iteration (O5) with the 3-D operator. */
+void wmco3_solve(const double* f, const double* u0, int64_t D, int64_t H, int64_t W, double lam,
+                 double delta, int iters, double* Uout) {
+    const int64_t n = D * H * W;
+    double* a = (double*)malloc(sizeof(double) * n);
+    double* h = (double*)malloc(sizeof(double) * n);
+    memcpy(a, u0 ? u0 : f, sizeof(double) * n);
+    for (int t = 0; t < iters; ++t) {
+        wmco3_compute(a, D, H, W, h, NULL);
+        for (int64_t k = 0; k < n; ++k)
+            a[k] = f ? a[k] + delta * ((f[k] - a[k]) + lam * h[k]) : a[k] + delta * h[k];
+    }
+    memcpy(Uout, a, sizeof(double) * n);
+    free(a);
+    free(h);
 }

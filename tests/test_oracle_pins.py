@@ -890,3 +890,107 @@ def test_network_module_kernel_table_matches_the_oracle():
     transcribed separately from Sec. 4.2; they must agree entry for entry."""
     from paper_1903_07189_amd.nn import PRINTED_KERNELS_X12
     assert np.array_equal(np.array(PRINTED_KERNELS_X12), oracle.kernel_table())
+
+
+# ---- 3-D extension (O13) --------------------------------------------------------------
+
+def _fold_kernels(base, normals):
+    """Half windows by Neumann reflection of `base` (centre excluded) across
+    each mirror plane through the centre: for normal n and each side, weights
+    on the dropped side move to their mirror image.  Dimension-generic."""
+    nd = base.ndim
+    out = []
+    for n in normals:
+        n = np.array(n)
+        for sg in (1, -1):  # keep sg * n.o <= 0
+            k = np.zeros_like(base)
+            for idx in np.ndindex(base.shape):
+                o = np.array(idx) - 1
+                if not o.any():
+                    continue
+                d = sg * int(n @ o)
+                t = o - 2 * int(n @ o) * n // int(n @ n) if d > 0 else o
+                k[tuple(t + 1)] += base[idx]
+            k[(1,) * nd] = -k.sum()
+            out.append(k)
+    return np.array(out)
+
+
+def test_fold_construction_reproduces_the_printed_2d_kernels():
+    """The construction used for 3-D, applied in 2-D to k4 (x12) with the four
+    mirror lines of the square, gives exactly the eight printed kernels of
+    Sec. 4.2 (as a set): the 3-D kernels follow the paper's own recipe."""
+    s = np.array([1, 2, 1])
+    k4 = np.outer(s, s).astype(np.int64)   # off-centre weights of 12 k4
+    k4[1, 1] = 0
+    folded = _fold_kernels(k4, [(0, 1), (1, 0), (1, 1), (1, -1)])
+    printed = oracle.kernel_table()
+    key = lambda a: sorted(map(lambda k: tuple(k.ravel()), a))  # noqa: E731
+    assert key(folded) == key(printed)
+
+
+def test_3d_kernels_match_an_independent_construction():
+    s = np.array([1, 2, 1])
+    base = np.einsum("i,j,k->ijk", s, s, s).astype(np.int64)  # [z][y][x]
+    base[1, 1, 1] = 0
+    # normals in (z, y, x) order for the [z][y][x] layout: e_x, e_y, e_z, e_x+-e_y, e_x+-e_z, e_y+-e_z
+    normals = [(0, 0, 1), (0, 1, 0), (1, 0, 0), (0, 1, 1), (0, -1, 1), (1, 0, 1), (-1, 0, 1),
+               (1, 1, 0), (-1, 1, 0)]
+    ref = _fold_kernels(base, normals)
+    k3 = oracle.kernels3()
+    assert np.array_equal(k3, ref)
+    # structure: 18 kernels, centre -56, off-centre weights >= 0 summing to 56,
+    # opposite sides of a plane add up to twice the base kernel
+    assert k3.shape == (18, 3, 3, 3)
+    assert np.all(k3.reshape(18, 27).sum(1) == 0) and np.all(k3[:, 1, 1, 1] == -56)
+    full = base.copy()
+    full[1, 1, 1] = -56
+    for j in range(9):
+        assert np.array_equal(k3[2 * j] + k3[2 * j + 1], 2 * full)
+
+
+def test_3d_operator_against_library_correlation():
+    """compute3 = first-argmin over the 18 kernels applied with
+    scipy.ndimage.correlate (replicate border), divided by 56."""
+    from scipy import ndimage
+    rng = np.random.default_rng(50)
+    for shape in [(1, 1, 1), (2, 3, 4), (5, 6, 7), (9, 4, 11)]:
+        U = rng.uniform(0, 1, size=shape)
+        resp = np.stack([ndimage.correlate(U, k.astype(np.float64), mode="nearest")
+                         for k in oracle.kernels3()])
+        m = np.argmin(np.abs(resp), axis=0)
+        ref = np.take_along_axis(resp, m[None], 0)[0] / 56.0
+        H, mo = oracle.compute3(U, return_argmin=True)
+        assert np.allclose(H, ref, atol=1e-13)
+        # the selection agrees wherever the minimum is not a rounding-level tie
+        a = np.sort(np.abs(resp), axis=0)
+        clear = (a[1] - a[0]) > 1e-9
+        assert np.array_equal(mo[clear], m[clear])
+
+
+def test_3d_closed_forms_and_symmetry():
+    rng = np.random.default_rng(51)
+    # constants -> 0 exactly
+    assert np.all(oracle.compute3(np.full((4, 5, 6), 0.7)) == 0.0)
+    # linear along an axis or a face diagonal -> 0 in the interior
+    z, y, x = np.mgrid[0:7, 0:8, 0:9].astype(np.float64)
+    for U in (0.5 * x, -0.25 * y, 2.0 * z, x + y, x - z, y + z):
+        assert np.all(oracle.compute3(U)[1:-1, 1:-1, 1:-1] == 0.0)
+    # paraboloid centred on a voxel: all 18 candidates tie at
+    # (8*1*3 + 12*2*2 + 6*4*1)/56 = 96/56 = 12/7
+    c = 3
+    U = (x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2
+    assert oracle.compute3(U)[c, c, c] == 96.0 / 56.0
+    # the cube's symmetries permute the kernels: H commutes with them on
+    # generic data
+    U = rng.uniform(0, 1, size=(6, 7, 8))
+    H = oracle.compute3(U)
+    assert np.allclose(oracle.compute3(U[::-1]), H[::-1], atol=1e-14)
+    assert np.allclose(oracle.compute3(U.transpose(0, 2, 1)), H.transpose(0, 2, 1), atol=1e-14)
+    assert np.allclose(oracle.compute3(U.transpose(2, 1, 0)), H.transpose(2, 1, 0), atol=1e-14)
+    # the solver is the explicit iteration
+    f = rng.uniform(0, 1, size=(4, 5, 6))
+    a = f.copy()
+    for _ in range(3):
+        a = a + 0.5 * ((f - a) + 1.0 * oracle.compute3(a))
+    assert np.allclose(oracle.solve3(f, 1.0, 3), a, atol=1e-14)
