@@ -374,6 +374,17 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side):
                     "note": "backward = segment recompute (none at period 1) + adjoint steps "
                             "+ lam reduction"}
         del x
+    # 3-D extension: one 256^3 volume, operator and data-term Jacobi steps
+    vol = torch.rand((256, 256, 256), device=f.device)
+    h3 = wmc.compute3(vol)
+    ms_c3 = timed(lambda: wmc.compute3(vol), 10, stream, torch) / 10
+    wmc.solve3(vol, 1.0, 10)
+    ms_s3 = timed(lambda: wmc.solve3(vol, 1.0, 10), 3, stream, torch) / 3
+    nv = vol.numel()
+    ex["volume_256cubed"] = {"compute_gvox_s": round(nv / (ms_c3 * 1e-3) / 1e9, 1),
+                             "solve_gvox_iter_s": round(nv * 10 / (ms_s3 * 1e-3) / 1e9, 1),
+                             "note": "18 half windows, one sweep per launch"}
+    del vol, h3
     # learnable half-window layer, 8 kernels, on the 16 x 512^2 batch
     xw = torch.from_numpy(wmc_synth.c4()[0][:, 0]).to(f.device)
     kw = wmc.nn.printed_kernels(device=f.device)

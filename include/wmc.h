@@ -254,6 +254,40 @@ int wmc_fd_flow(const float* u0, float* u_out, int iters, float dt, float eps, v
                 size_t ws_bytes, wmc_shape s, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * 3-D volumes.  The conclusion of the paper mentions the extension to 3-D
+ * images without giving kernels; these entry points build them the way
+ * Sec. 4.1 builds the 2-D ones: the tensor-product isotropic Laplacian
+ * (s x s x s - 64 delta)/56, s = [1 2 1], reflected across each of the 9
+ * mirror planes of the 3x3x3 window (normals e_x, e_y, e_z, e_x +- e_y,
+ * e_x +- e_z, e_y +- e_z), one candidate per plane side, 18 in all (order:
+ * plane 0..8, side n.o <= 0 first); the minimum-magnitude activation with
+ * first-index ties; replicate border.
+ *
+ * wmc_shape3: n volumes of d x h x w; element (v, z, y, x) at
+ * v*vs + z*ss + y*ld + x (row stride ld >= w, slice stride
+ * ss >= (h-1)*ld + w, volume stride vs >= (d-1)*ss + (h-1)*ld + w when n > 1).
+ *
+ * wmc3_compute -- H(u) for every voxel.
+ * wmc3_step    -- one Jacobi update: u_out = u + dt[(f - u) + lam H(u)]
+ *                 (f NULL: u + dt H(u)); dt <= 0 selects 1/(1+lam) (data)
+ *                 or 1 (flow); lam: device array of n values (data mode).
+ * wmc3_solve   -- iters such updates from u0 (NULL: f); ws: one volume set
+ *                 (vs*n or the extent, floats) when iters >= 2.
+ * Single sweeps per launch (no temporal blocking); the same errors as the
+ * 2-D entry points.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t n, d, h, w, ld, ss, vs;
+} wmc_shape3;
+
+int wmc3_compute(const float* u, float* hw, wmc_shape3 s, void* stream);
+int wmc3_step(const float* u, const float* f, float* u_out, const float* lam, float dt,
+              wmc_shape3 s, void* stream);
+size_t wmc3_solve_workspace(wmc_shape3 s);
+int wmc3_solve(const float* f, const float* u0, float* u_out, const float* lam, int iters,
+               float dt, void* ws, size_t ws_bytes, wmc_shape3 s, void* stream);
+
+/* ---------------------------------------------------------------------------
  * wmc_workspace_bytes -- one query for every workspace size:
  *   WMC_OP_SOLVE, WMC_OP_FD_FLOW   wmc_solve_workspace(s)
  *   WMC_OP_SOLVE_L1                wmc_l1_workspace(s)

@@ -15,7 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libwmc.so")
 
-SOURCES = ["wmc_stream.hip", "wmc_adjoint.hip", "wmc_aux.hip", "wmc_layer.hip", "wmc_api.cpp"]
+SOURCES = ["wmc_stream.hip", "wmc_adjoint.hip", "wmc_aux.hip", "wmc_layer.hip", "wmc_3d.hip",
+           "wmc_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1481,6 +1481,119 @@ size_t wmc_workspace_bytes(int op, wmc_shape s, int iters, int ckpt_every) {
     }
 }
 
+// ---- 3-D volumes -------------------------------------------------------------
+namespace {
+
+int64_t extent3(const wmc_shape3& s) {
+    return (s.n - 1) * s.vs + (s.d - 1) * s.ss + (s.h - 1) * s.ld + s.w;
+}
+
+int check_shape3(const wmc_shape3& s) {
+    if (s.n < 1 || s.d < 1 || s.h < 1 || s.w < 1)
+        return fail(WMC_EINVAL, "shape3: n, d, h and w must be >= 1");
+    if (s.d >= kMaxSide || s.h >= kMaxSide || s.w >= kMaxSide)
+        return fail(WMC_EINVAL, "shape3: d, h and w must be < 2^30");
+    if (s.n > 65535) return fail(WMC_EINVAL, "shape3: at most 65535 volumes per call");
+    if (s.ld < s.w) return fail(WMC_EINVAL, "shape3: ld must be >= w");
+    if (s.d > 1 && s.ss < (s.h - 1) * s.ld + s.w)
+        return fail(WMC_EINVAL, "shape3: ss must be >= (h-1)*ld + w when d > 1");
+    if (s.n > 1 && s.vs < (s.d - 1) * s.ss + (s.h - 1) * s.ld + s.w)
+        return fail(WMC_EINVAL, "shape3: vs must be >= (d-1)*ss + (h-1)*ld + w when n > 1");
+    if (s.ss < 0 || s.vs < 0) return fail(WMC_EINVAL, "shape3: strides must be >= 0");
+    if (s.n * s.h * ((s.w + 61) / 62) > (int64_t)1 << 31)
+        return fail(WMC_EINVAL, "shape3: too many rows for one launch");
+    return WMC_OK;
+}
+
+int64_t set_stride3(const wmc_shape3& s) {
+    const int64_t e = extent3(s), nv = s.n * s.vs;
+    return nv >= e ? nv : e;
+}
+
+}  // namespace
+
+int wmc3_compute(const float* u, float* hw, wmc_shape3 s, void* stream) {
+    g_err.clear();
+    int rc = check_shape3(s);
+    if (rc) return rc;
+    if (!u || !hw) return fail(WMC_EINVAL, "wmc3_compute: null pointer");
+    const int64_t ext = extent3(s);
+    if (overlaps(range_of(u, ext, 4), range_of(hw, ext, 4)))
+        return fail(WMC_EINVAL, "wmc3_compute: output overlaps input");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    const hipError_t e = launch_stream3d(u, nullptr, hw, nullptr, 0.0f, kModeCompute, s.n, s.d, s.h,
+                                         s.w, s.ld, s.ss, s.vs, as_stream(stream));
+    return e == hipSuccess ? WMC_OK : hip_fail(e, "wmc3_compute launch");
+}
+
+int wmc3_step(const float* u, const float* f, float* u_out, const float* lam, float dt,
+              wmc_shape3 s, void* stream) {
+    g_err.clear();
+    int rc = check_shape3(s);
+    if (rc) return rc;
+    if (!u || !u_out) return fail(WMC_EINVAL, "wmc3_step: null pointer");
+    if (f && !lam) return fail(WMC_EINVAL, "wmc3_step: lam is required with a data term");
+    if (!std::isfinite(dt)) return fail(WMC_EINVAL, "wmc3_step: dt must be finite");
+    const int64_t ext = extent3(s);
+    const Range ro = range_of(u_out, ext, 4);
+    if (overlaps(ro, range_of(u, ext, 4)) || overlaps(ro, range_of(f, ext, 4)))
+        return fail(WMC_EINVAL, "wmc3_step: u_out overlaps an input (updates are synchronous)");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    const hipError_t e = launch_stream3d(u, f, u_out, lam, dt, f ? kModeData : kModeFlow, s.n, s.d,
+                                         s.h, s.w, s.ld, s.ss, s.vs, as_stream(stream));
+    return e == hipSuccess ? WMC_OK : hip_fail(e, "wmc3_step launch");
+}
+
+size_t wmc3_solve_workspace(wmc_shape3 s) {
+    if (check_shape3(s)) return 0;
+    return (size_t)set_stride3(s) * sizeof(float);
+}
+
+int wmc3_solve(const float* f, const float* u0, float* u_out, const float* lam, int iters,
+               float dt, void* ws, size_t ws_bytes, wmc_shape3 s, void* stream) {
+    g_err.clear();
+    int rc = check_shape3(s);
+    if (rc) return rc;
+    if (!u_out) return fail(WMC_EINVAL, "wmc3_solve: null u_out");
+    if (!f && !u0) return fail(WMC_EINVAL, "wmc3_solve: the flow (f == NULL) needs u0");
+    if (f && !lam) return fail(WMC_EINVAL, "wmc3_solve: lam is required with a data term");
+    if (iters < 0 || !std::isfinite(dt)) return fail(WMC_EINVAL, "wmc3_solve: bad iters or dt");
+    const int64_t ext = extent3(s);
+    if (iters >= 2 && (!ws || ws_bytes < wmc3_solve_workspace(s)))
+        return fail(WMC_ENOMEM, "wmc3_solve: workspace smaller than wmc3_solve_workspace()");
+    const float* src0 = u0 ? u0 : f;
+    const Range ro = range_of(u_out, ext, 4), rw = range_of(iters >= 2 ? ws : nullptr, ext, 4);
+    for (const Range& r : {range_of(src0, ext, 4), range_of(f, ext, 4)})
+        if (overlaps(ro, r) || overlaps(rw, r)) return fail(WMC_EINVAL, "wmc3_solve: buffers overlap");
+    if (overlaps(ro, rw)) return fail(WMC_EINVAL, "wmc3_solve: u_out overlaps ws");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t st = as_stream(stream);
+    if (iters == 0) {
+        // copy each volume's slices row by row
+        for (int64_t v = 0; v < s.n; ++v) {
+            const hipError_t e = launch_copy_planes(src0 + v * s.vs, u_out + v * s.vs, s.d, s.h, s.w,
+                                                    s.ld, s.ss, st);
+            if (e != hipSuccess) return hip_fail(e, "copy");
+        }
+        return WMC_OK;
+    }
+    const float* src = src0;
+    for (int t = 0; t < iters; ++t) {
+        float* dst = ((iters - 1 - t) % 2 == 0) ? u_out : static_cast<float*>(ws);
+        const hipError_t e = launch_stream3d(src, f, dst, lam, dt, f ? kModeData : kModeFlow, s.n,
+                                             s.d, s.h, s.w, s.ld, s.ss, s.vs, st);
+        if (e != hipSuccess) return hip_fail(e, "wmc3_solve launch");
+        src = dst;
+    }
+    return WMC_OK;
+}
+
 int wmc_fd_compute(const float* u, float* hw, float eps, wmc_shape s, void* stream) {
     g_err.clear();
     int rc = check_shape(s);

@@ -114,6 +114,11 @@ hipError_t launch_layer_backward(const float* u, const float* w, int K, const ui
                                  const float* g, float* g_u, float* part, float* g_w, int64_t n,
                                  int64_t h, int64_t wd, int64_t ld, int64_t ps, hipStream_t st);
 
+// 3-D volumes (wmc_3d.hip).
+hipError_t launch_stream3d(const float* u, const float* f, float* out, const float* lam, float dt,
+                           int mode, int64_t n, int64_t d, int64_t h, int64_t w, int64_t ld,
+                           int64_t ss, int64_t vs, hipStream_t st);
+
 // Auxiliary kernels (wmc_aux.hip).
 hipError_t launch_fd(const float* u, float* out, int64_t n, int64_t h, int64_t w, int64_t ld,
                      int64_t ps, float dt, float eps, bool flow, hipStream_t st);

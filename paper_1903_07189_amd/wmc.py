@@ -35,6 +35,12 @@ class Shape(ctypes.Structure):
                 ("ld", ctypes.c_int64), ("ps", ctypes.c_int64)]
 
 
+class Shape3(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int64), ("h", ctypes.c_int64),
+                ("w", ctypes.c_int64), ("ld", ctypes.c_int64), ("ss", ctypes.c_int64),
+                ("vs", ctypes.c_int64)]
+
+
 class Image(ctypes.Structure):
     _fields_ = [("u0", ctypes.c_void_p), ("f", ctypes.c_void_p), ("out", ctypes.c_void_p),
                 ("h", ctypes.c_int64), ("w", ctypes.c_int64), ("ld", ctypes.c_int64),
@@ -51,6 +57,7 @@ EXPORTS = ["wmc_compute", "wmc_step", "wmc_solve_workspace", "wmc_set_stride",
            "wmc_num_checkpoints", "wmc_solve", "wmc_solve_tuning", "wmc_l1_workspace",
            "wmc_solve_l1", "wmc_fd_compute", "wmc_fd_flow", "wmc_layer_workspace",
            "wmc_layer_forward", "wmc_layer_backward", "wmc_workspace_bytes",
+           "wmc3_compute", "wmc3_step", "wmc3_solve_workspace", "wmc3_solve",
            "wmc_batched_workspace", "wmc_solve_batched", "wmc_autotune", "wmc_backward_workspace",
            "wmc_backward", "wmc_selftest", "wmc_last_error", "wmc_release"]
 
@@ -80,6 +87,11 @@ def lib():
     L.wmc_solve_l1.argtypes = [P, P, P, P, P, P, F, I, F, ctypes.POINTER(Tuning), P, SZ, Shape, P]
     L.wmc_fd_compute.argtypes = [P, P, F, Shape, P]
     L.wmc_fd_flow.argtypes = [P, P, I, F, F, P, SZ, Shape, P]
+    L.wmc3_compute.argtypes = [P, P, Shape3, P]
+    L.wmc3_step.argtypes = [P, P, P, P, F, Shape3, P]
+    L.wmc3_solve_workspace.argtypes = [Shape3]
+    L.wmc3_solve_workspace.restype = SZ
+    L.wmc3_solve.argtypes = [P, P, P, P, I, F, P, SZ, Shape3, P]
     L.wmc_workspace_bytes.argtypes = [I, Shape, I, I]
     L.wmc_workspace_bytes.restype = SZ
     L.wmc_layer_workspace.argtypes = [Shape, I]
@@ -101,6 +113,7 @@ def lib():
     L.wmc_release.restype = None
     for name in ("wmc_compute", "wmc_step", "wmc_solve", "wmc_solve_tuning", "wmc_solve_l1",
                  "wmc_fd_compute", "wmc_fd_flow", "wmc_layer_forward", "wmc_layer_backward",
+                 "wmc3_compute", "wmc3_step", "wmc3_solve",
                  "wmc_solve_batched",
                  "wmc_autotune",
                  "wmc_backward", "wmc_selftest"):
@@ -336,6 +349,51 @@ class WMCKernelLayer(torch.autograd.Function):
         if g_w is not None:
             g_w = g_w.to(w.dtype)
         return g_u, g_w
+
+
+def _volumes(t: torch.Tensor) -> torch.Tensor:
+    if t.dim() == 3:
+        t = t.unsqueeze(0)
+    if t.dim() != 4:
+        raise ValueError("expected a (D, H, W) or (N, D, H, W) tensor")
+    if t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError("expected a float32 CUDA tensor")
+    return t.contiguous()
+
+
+def shape3_of(t: torch.Tensor) -> Shape3:
+    n, d, h, w = t.shape
+    return Shape3(n, d, h, w, t.stride(2), t.stride(1), t.stride(0) if n > 1 else d * t.stride(1))
+
+
+def compute3(u: torch.Tensor) -> torch.Tensor:
+    """3-D half-window operator (18 half windows of the tensor-product
+    Laplacian; the extension the conclusion mentions)."""
+    squeeze = u.dim() == 3
+    u = _volumes(u)
+    out = torch.empty_like(u)
+    check(lib().wmc3_compute(_ptr(u), _ptr(out), shape3_of(u), _stream()))
+    return out[0] if squeeze else out
+
+
+def solve3(f: torch.Tensor | None, lam=1.0, iters: int = 1, dt: float = 0.0,
+           u0: torch.Tensor | None = None) -> torch.Tensor:
+    """iters Jacobi updates of the data (f given) or flow iteration on volumes."""
+    ref = f if f is not None else u0
+    if ref is None:
+        raise ValueError("need f or u0")
+    squeeze = ref.dim() == 3
+    ref = _volumes(ref)
+    f = None if f is None else _volumes(f)
+    u0 = None if u0 is None else _volumes(u0)
+    s = shape3_of(ref)
+    L = lib()
+    out = torch.empty_like(ref)
+    ws = torch.empty(max(1, L.wmc3_solve_workspace(s) // 4), dtype=torch.float32, device=ref.device)
+    lt = _lam_tensor(lam, ref.shape[0], ref.device) if f is not None else None
+    check(L.wmc3_solve(_ptr(f), _ptr(u0), _ptr(out), _ptr(lt), int(iters), float(dt), _ptr(ws),
+                       ws.numel() * 4, s, _stream()))
+    return out[0] if squeeze else out
 
 
 def solve_tuning(f: torch.Tensor | None, lam=1.0, dt: float = 0.0, u0: torch.Tensor | None = None):

@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "wmc.h")
 def _declared_functions():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(wmc_[a-z_0-9]+)\s*\(", txt, re.M)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(wmc[0-9]?_[a-z_0-9]+)\s*\(", txt, re.M)
     return sorted(set(names))
 
 

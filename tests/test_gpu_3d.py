@@ -1,0 +1,123 @@
+"""The 3-D extension (18 half windows of the tensor-product Laplacian) on
+the GPU against the oracle (O13).
+
+Tolerances: each candidate is a sum of 26 weighted taps (weights 1..8,
+values in [0, 1]) in FP32, so |S| <~ 64 with an error of a few ulps:
+2e-6 on H = S/56.  Where two candidates of different value are within
+TAU = 1e-4 (x56 units) in magnitude FP32 and FP64 may select differently;
+there the GPU value must be one of the near-minimal candidates."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-6
+TAU = 1e-4
+
+
+@pytest.fixture(scope="module")
+def wmc():
+    import paper_1903_07189_amd as W
+    W.lib()
+    return W
+
+
+def to_gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0")
+
+
+def candidates(U):
+    from scipy import ndimage
+    return np.stack([ndimage.correlate(U, k.astype(np.float64), mode="nearest")
+                     for k in oracle.kernels3()])
+
+
+def check_h(U, h):
+    U = U.astype(np.float64)
+    ref = oracle.compute3(U)
+    bad = np.abs(h - ref) > TOL
+    if bad.any():
+        S = candidates(U)
+        mn = np.abs(S).min(axis=0)
+        ok = np.any((np.abs(S) <= mn + TAU) & (np.abs(S / 56.0 - h[None]) <= TOL), axis=0)
+        assert ok[bad].all()
+        assert bad.mean() < 1e-3
+    return bad.sum()
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 4), (5, 7, 9), (4, 1, 70), (17, 33, 70),
+                                   (9, 65, 130)])
+def test_compute3_parity(wmc, shape):
+    U = np.random.default_rng(sum(shape)).uniform(0, 1, size=shape).astype(np.float32)
+    h = wmc.compute3(to_gpu(U)).cpu().numpy()
+    check_h(U, h)
+
+
+def test_compute3_exact_cases(wmc):
+    z, y, x = np.mgrid[0:9, 0:10, 0:11].astype(np.float32)
+    assert torch.count_nonzero(wmc.compute3(to_gpu(np.full((5, 6, 7), 0.7, np.float32)))) == 0
+    for U in (0.5 * x, -0.25 * y, 2.0 * z, x + y, x - z, y + z):
+        h = wmc.compute3(to_gpu(U)).cpu().numpy()
+        assert np.all(h[1:-1, 1:-1, 1:-1] == 0.0)
+    c = 4
+    U = (x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2
+    h = wmc.compute3(to_gpu(U)).cpu().numpy()
+    assert abs(h[c, c, c] - 12.0 / 7.0) <= 1e-6
+
+
+def test_volumes_and_strides(wmc):
+    rng = np.random.default_rng(3)
+    U = rng.uniform(0, 1, size=(3, 6, 20, 90)).astype(np.float32)
+    h = wmc.compute3(to_gpu(U)).cpu().numpy()
+    for v in range(3):
+        check_h(U[v], h[v])
+    # a padded layout through the raw ABI
+    from paper_1903_07189_amd import wmc as M
+    n, d, hh, w, ld = 2, 5, 7, 33, 40
+    ss, vs = hh * ld + 8, d * (hh * ld + 8) + 16
+    base = rng.uniform(0, 1, size=n * vs).astype(np.float32)
+    src = to_gpu(base)
+    out = torch.full((n * vs,), float("nan"), device="cuda:0")
+    import ctypes
+    M.check(M.lib().wmc3_compute(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                 M.Shape3(n, d, hh, w, ld, ss, vs), None))
+    o = out.cpu().numpy()
+    for v in range(n):
+        vol = np.stack([base[v * vs + z * ss: v * vs + z * ss + hh * ld].reshape(hh, ld)[:, :w]
+                        for z in range(d)])
+        got = np.stack([o[v * vs + z * ss: v * vs + z * ss + hh * ld].reshape(hh, ld) for z in range(d)])
+        check_h(vol, got[:, :, :w])
+        assert np.isnan(got[:, :, w:]).all()
+
+
+@pytest.mark.parametrize("mcf", [False, True])
+def test_solve3_parity(wmc, mcf):
+    rng = np.random.default_rng(7)
+    f = rng.uniform(0, 1, size=(12, 20, 70)).astype(np.float32)
+    F = to_gpu(f)
+    # one step: tie-aware like the operator
+    if mcf:
+        u1 = wmc.solve3(None, iters=1, u0=F).cpu().numpy()
+        r1 = oracle.solve3(None, iters=1, u0=f)
+    else:
+        u1 = wmc.solve3(F, 1.5, 1).cpu().numpy()
+        r1 = oracle.solve3(f, 1.5, 1)
+    d = np.abs(u1 - r1)
+    assert (d > 1e-5).mean() < 1e-3 and d.max() < 0.05
+    # k steps in one call = k single-step calls, bitwise
+    lam = 1.5
+    u = F
+    for _ in range(5):
+        u = wmc.solve3(F, lam, 1, u0=u) if not mcf else wmc.solve3(None, iters=1, u0=u)
+    uk = wmc.solve3(F, lam, 5) if not mcf else wmc.solve3(None, iters=5, u0=F)
+    assert torch.equal(u, uk)
+    # 10 free-running steps against FP64 (flips near ties decay in data mode)
+    if not mcf:
+        g = wmc.solve3(F, lam, 10).cpu().numpy()
+        r = oracle.solve3(f, lam, 10)
+        assert np.abs(g - r).mean() < 1e-5 and np.abs(g - r).max() < 0.05
+        # maximum principle of the default step
+        assert g.min() >= f.min() - 1e-6 and g.max() <= f.max() + 1e-6
