@@ -121,3 +121,28 @@ def test_solve3_parity(wmc, mcf):
         assert np.abs(g - r).mean() < 1e-5 and np.abs(g - r).max() < 0.05
         # maximum principle of the default step
         assert g.min() >= f.min() - 1e-6 and g.max() <= f.max() + 1e-6
+
+
+def test_volume_beyond_2_pow_31_elements(wmc):
+    """A 1300^3 volume (2.2e9 voxels): 64-bit plane offsets; sampled voxels
+    against the oracle on local windows."""
+    n = 1300
+    g = torch.Generator(device="cuda:0").manual_seed(3)
+    v = torch.rand((n, n, n), device="cuda:0", generator=g)
+    h = wmc.compute3(v)
+    rng = np.random.default_rng(4)
+    pts = [(n - 1, n - 1, n - 1), (n - 1, 0, n - 1), (0, n - 1, 0)]
+    pts += [tuple(int(c) for c in rng.integers(0, n, 3)) for _ in range(12)]
+    for (z, y, x) in pts:
+        z0, z1 = max(0, z - 1), min(n, z + 2)
+        y0, y1 = max(0, y - 1), min(n, y + 2)
+        x0, x1 = max(0, x - 1), min(n, x + 2)
+        cu = v[z0:z1, y0:y1, x0:x1].cpu().numpy().astype(np.float64)
+        got = float(h[z, y, x])
+        ref = oracle.compute3(cu)[z - z0, y - y0, x - x0]
+        if abs(got - ref) > TOL:
+            S = candidates(cu)[:, z - z0, y - y0, x - x0]
+            mn = np.abs(S).min()
+            assert np.any((np.abs(S) <= mn + TAU) & (np.abs(S / 56.0 - got) <= TOL))
+    del v, h
+    torch.cuda.empty_cache()

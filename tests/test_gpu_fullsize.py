@@ -65,3 +65,43 @@ def test_denoising_quality(setup):
     e_in = np.sqrt(((noisy[0] - clean[0]) ** 2).mean())
     e_out = np.sqrt(((out - clean[0]) ** 2).mean())
     assert e_out < 0.8 * e_in
+
+
+def test_planes_beyond_2_pow_30_elements():
+    """Two planes of 23000 x 47000 (each more than 2^30 elements, so plane
+    offsets pass 2^31): one step, the operator and a 3-sweep fused solve,
+    sampled against the oracle on local windows (exact: the window is cut
+    only by the true image border or at least k pixels from the sample)."""
+    import paper_1903_07189_amd as W
+    H, Wd = 23000, 47000
+    assert H * Wd > 2 ** 30
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    u = torch.rand((2, H, Wd), device="cuda:0", generator=g)
+    f = torch.rand((2, H, Wd), device="cuda:0", generator=g)
+    lam = torch.tensor([1.0, 2.0], device="cuda:0")
+    u1 = W.step(u, f, lam)
+    h = W.compute(u)
+    u3 = W.solve(f, lam, 3, u0=u, tuning={"cols": 2, "tsteps": 3, "seg_rows": 64})
+    rng = np.random.default_rng(9)
+    pts = [(1, H - 1, Wd - 1), (1, H - 1, 0), (1, 0, Wd - 1), (0, 0, 0), (1, H // 2, Wd - 2)]
+    pts += [(int(rng.integers(0, 2)), int(rng.integers(0, H)), int(rng.integers(0, Wd)))
+            for _ in range(20)]
+    for (p, y, x) in pts:
+        for k, got in ((1, u1), (3, u3)):
+            y0, y1 = max(0, y - k), min(H, y + k + 1)
+            x0, x1 = max(0, x - k), min(Wd, x + k + 1)
+            cu = u[p, y0:y1, x0:x1].cpu().numpy().astype(np.float64)
+            cf = f[p, y0:y1, x0:x1].cpu().numpy().astype(np.float64)
+            ref = oracle.step_window(cu, cf, y - y0, x - x0, k, lam=float(lam[p]))
+            val = float(got[p, y, x])
+            if abs(val - ref) > 1e-5:  # only through a near tie of the selection
+                assert k == 1 and oracle.near_tie_mask(cu, 1e-4)[y - y0, x - x0], (p, y, x, k)
+        y0, y1 = max(0, y - 1), min(H, y + 2)
+        x0, x1 = max(0, x - 1), min(Wd, x + 2)
+        cu = u[p, y0:y1, x0:x1].cpu().numpy().astype(np.float64)
+        hr = oracle.compute(cu)[y - y0, x - x0]
+        hv = float(h[p, y, x])
+        if abs(hv - hr) > 1e-5:
+            assert oracle.near_tie_mask(cu, 1e-4)[y - y0, x - x0], (p, y, x)
+    del u, f, u1, h, u3
+    torch.cuda.empty_cache()
