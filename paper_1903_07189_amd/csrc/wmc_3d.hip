@@ -247,8 +247,10 @@ __global__ __launch_bounds__(256) void k_stream3d(Vol3Args A) {
     }
 }
 
+// ~16K work items, 8..128 planes per item.  (Round-filling row counts, which
+// help the 2-D kernels, measured slower here: this kernel hides latency
+// better with more, shorter items.)
 static int vol_rows(int64_t n, int64_t d, int64_t h, int64_t strips) {
-    // ~16K work items, 8..128 planes per item
     const int64_t cols = n * h * strips;
     int R = 8;
     while (R < 128 && cols * ((d + R - 1) / R) > 16384) R *= 2;

@@ -33,6 +33,26 @@ __host__ __device__ inline int strip_count(int W, int C, int T) {
 
 __host__ __device__ inline int seg_count(int H, int R) { return (H + R - 1) / R; }
 
+// Rows per work item for a launch of equal one-wave items, `cols` columns of
+// items (strips x planes), each covering R rows out of h: the largest R whose
+// item count fills whole rounds of the `slots` resident waves (k = 1, 2, ...),
+// at least rmin.  Items just past a multiple of the slots would cost a
+// nearly empty extra round.
+inline int fill_rows(int64_t cols, int64_t h, int64_t slots, int rmin, int rmax) {
+    if (slots < 1) slots = 1;
+    for (int64_t k = 1; k <= 64; ++k) {
+        const int64_t nseg = (k * slots) / (cols > 0 ? cols : 1);
+        if (nseg < 1) continue;
+        const int64_t R = (h + nseg - 1) / nseg;
+        if (R < rmin) break;
+        if (R <= rmax) return (int)R;
+    }
+    return rmin < h ? rmin : (int)h;
+}
+
+// Resident waves of a kernel launched with `block` threads (occupancy API x CUs).
+int64_t kernel_slots(const void* fn, int block, size_t dyn_lds);
+
 // One image (all its channels) as seen by the kernels.
 struct ImageDesc {
     const float* src0;  // state read by a launch with src_sel == 0

@@ -351,38 +351,52 @@ __global__ __launch_bounds__(256) void k_layer_wreduce(const float* __restrict__
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-static int layer_rows(int64_t n, int64_t h, int64_t strips, int64_t target) {
-    const int64_t rows_total = n * h * strips;
-    int R = 16;
-    while (R < 256 && rows_total / R > target) R *= 2;
-    return R;
-}
-
 static int layer_chunk(int K) { return K < kBwdChunk ? K : kBwdChunk; }
 
-int layer_fwd_items(int64_t n, int64_t h, int64_t w, int* R, int* nstrip, int* nseg) {
+using LayerFwdFn = void (*)(LayerFwdArgs);
+using LayerBwdFn = void (*)(LayerBwdArgs);
+
+static LayerFwdFn fwd_fn(int K) {
+    static const LayerFwdFn tab[9] = {k_layer_fwd<0>, k_layer_fwd<1>, k_layer_fwd<2>,
+                                      k_layer_fwd<3>, k_layer_fwd<4>, k_layer_fwd<5>,
+                                      k_layer_fwd<6>, k_layer_fwd<7>, k_layer_fwd<8>};
+    return tab[K <= 8 ? K : 0];
+}
+
+static LayerBwdFn bwd_fn(int KC) {
+    static const LayerBwdFn tab[9] = {nullptr, k_layer_bwd<1>, k_layer_bwd<2>, k_layer_bwd<3>,
+                                      k_layer_bwd<4>, k_layer_bwd<5>, k_layer_bwd<6>,
+                                      k_layer_bwd<7>, k_layer_bwd<8>};
+    return tab[KC];
+}
+
+// Row counts that fill whole rounds of resident waves (the backward's item
+// count is also the size of its partial-sum buffer, so it depends only on
+// the shape and K, never on pointers).
+int layer_fwd_items(int64_t n, int64_t h, int64_t w, int K, int* R, int* nstrip, int* nseg) {
     *nstrip = (int)((w + kFwdStep - 1) / kFwdStep);
-    *R = layer_rows(n, h, *nstrip, 8192);
+    const int64_t slots = kernel_slots(reinterpret_cast<const void*>(fwd_fn(K)), 256, 0);
+    *R = fill_rows(n * (int64_t)(*nstrip), h, slots, 8, 256);
     *nseg = seg_count((int)h, *R);
     return (int)std::min<int64_t>(n * (int64_t)(*nstrip) * (*nseg), 0x7fffffff);
 }
 
-int64_t layer_bwd_items(int64_t n, int64_t h, int64_t w, int* R, int* nstrip, int* nseg) {
+int64_t layer_bwd_items(int64_t n, int64_t h, int64_t w, int K, int* R, int* nstrip, int* nseg) {
     *nstrip = (int)((w + kBwdStep - 1) / kBwdStep);
-    *R = layer_rows(n, h, *nstrip, 4096);
+    const int KC = layer_chunk(K);
+    const int nchunk = (K + KC - 1) / KC;
+    const int64_t slots = kernel_slots(reinterpret_cast<const void*>(bwd_fn(KC)), 256, 0);
+    *R = fill_rows(n * (int64_t)(*nstrip) * nchunk, h, slots, 8, 256);
     *nseg = seg_count((int)h, *R);
     return n * (int64_t)(*nstrip) * (*nseg);
 }
 
 int64_t layer_part_floats(int64_t n, int64_t h, int64_t w, int K) {
     int R, ns, nsg;
-    const int64_t items = layer_bwd_items(n, h, w, &R, &ns, &nsg);
+    const int64_t items = layer_bwd_items(n, h, w, K, &R, &ns, &nsg);
     const int KC = layer_chunk(K);
     return items * ((K + KC - 1) / KC) * 9 * KC;
 }
-
-using LayerFwdFn = void (*)(LayerFwdArgs);
-using LayerBwdFn = void (*)(LayerBwdArgs);
 
 hipError_t launch_layer_forward(const float* u, const float* w, int K, float* out, uint8_t* sel,
                                 int64_t n, int64_t h, int64_t wd, int64_t ld, int64_t ps,
@@ -400,14 +414,11 @@ hipError_t launch_layer_forward(const float* u, const float* w, int K, float* ou
     a.ps = ps;
     a.K = K;
     int R, ns, nsg;
-    layer_fwd_items(n, h, wd, &R, &ns, &nsg);
+    layer_fwd_items(n, h, wd, K, &R, &ns, &nsg);
     a.R = R;
     a.nstrip = ns;
     a.nseg = nsg;
-    static const LayerFwdFn tab[9] = {k_layer_fwd<0>, k_layer_fwd<1>, k_layer_fwd<2>,
-                                      k_layer_fwd<3>, k_layer_fwd<4>, k_layer_fwd<5>,
-                                      k_layer_fwd<6>, k_layer_fwd<7>, k_layer_fwd<8>};
-    const LayerFwdFn fn = tab[K <= 8 ? K : 0];
+    const LayerFwdFn fn = fwd_fn(K);
     const int64_t total = n * (int64_t)ns * nsg;
     hipLaunchKernelGGL(fn, dim3((unsigned)((total + 3) / 4)), dim3(256), 0, st, a);
     return hipGetLastError();
@@ -431,17 +442,14 @@ hipError_t launch_layer_backward(const float* u, const float* w, int K, const ui
     a.ps = ps;
     a.K = K;
     int R, ns, nsg;
-    const int64_t items = layer_bwd_items(n, h, wd, &R, &ns, &nsg);
+    const int64_t items = layer_bwd_items(n, h, wd, K, &R, &ns, &nsg);
     a.R = R;
     a.nstrip = ns;
     a.nseg = nsg;
     const int KC = layer_chunk(K);
     a.nchunk = g_w ? (K + KC - 1) / KC : 1;
-    static const LayerBwdFn tab[9] = {nullptr, k_layer_bwd<1>, k_layer_bwd<2>, k_layer_bwd<3>,
-                                      k_layer_bwd<4>, k_layer_bwd<5>, k_layer_bwd<6>,
-                                      k_layer_bwd<7>, k_layer_bwd<8>};
     const int64_t waves = items * a.nchunk;
-    hipLaunchKernelGGL(tab[KC], dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(bwd_fn(KC), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !g_w) return e;
     hipLaunchKernelGGL(k_layer_wreduce, dim3((unsigned)(9 * K)), dim3(256), 0, st, part, items,
