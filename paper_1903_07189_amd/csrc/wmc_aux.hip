@@ -37,6 +37,16 @@ __global__ __launch_bounds__(kAX* kAY) void k_fd(const float* __restrict__ u, fl
     out[(int64_t)blockIdx.z * ps + r0 + x] = flow ? __builtin_fmaf(dt, hw, c) : hw;
 }
 
+int64_t kernel_slots(const void* fn, int block, size_t dyn_lds) {
+    int dev = 0, ncu = 0, nb = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 1024;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, dyn_lds) != hipSuccess || nb < 1)
+        nb = 1;
+    return (int64_t)ncu * nb * (block / 64);
+}
+
 hipError_t launch_fd(const float* u, float* out, int64_t n, int64_t h, int64_t w, int64_t ld,
                      int64_t ps, float dt, float eps, bool flow, hipStream_t st) {
     const dim3 grid((unsigned)((w + kAX - 1) / kAX), (unsigned)((h + kAY - 1) / kAY), (unsigned)n);

@@ -501,16 +501,6 @@ hipError_t launch_stream_single(int C, int T, int mode, bool argmin, const Image
     return hipGetLastError();
 }
 
-int64_t kernel_slots(const void* fn, int block, size_t dyn_lds) {
-    int dev = 0, ncu = 0, nb = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 1024;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 1024;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, dyn_lds) != hipSuccess || nb < 1)
-        nb = 1;
-    return (int64_t)ncu * nb * (block / 64);
-}
-
 int stream_single_blocks_per_cu(int C, int T, int mode, bool argmin) {
     SingleFn fn = single_table(C, T, mode, argmin);
     if (!fn) return 0;
