@@ -33,8 +33,8 @@ METRIC = "Gpixel-iter/s of WMC step (fp32) and % HBM roofline; batched vs per-im
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz = 39.3
 # Arithmetic of one pixel update in the column-sum form (wmc_device.hpp):
-# row quantities 3 + odd/even parts 11 + candidates 8 + selection 14 + update 3.
-ALGO_OPS_PER_PX_ITER = 39
+# row quantities 3 + odd/even parts 10 + candidates 8 + selection 14 + update 3.
+ALGO_OPS_PER_PX_ITER = 38
 BYTES_PER_PX_PASS = 12         # read U and f, write U' once per pass over memory
 
 
@@ -187,6 +187,38 @@ def timed(fn, reps, stream, torch):
     return e0.elapsed_time(e1)
 
 
+_SPIN = {"cycles_per_ms": None}
+
+
+def timed_device(fn, reps, stream, torch):
+    """Device time of `reps` back-to-back calls of `fn`, with the host cost of
+    issuing them hidden: a bounded spin kernel holds the stream while the host
+    enqueues the calls, and the events bracket only the calls.  Returns
+    (ms, hidden) where `hidden` says whether the enqueue finished before the
+    spin did (else the figure still includes host time)."""
+    if _SPIN["cycles_per_ms"] is None:
+        cyc = 2_000_000
+        torch.cuda._sleep(cyc)
+        ms = timed(lambda: torch.cuda._sleep(cyc), 3, stream, torch) / 3
+        _SPIN["cycles_per_ms"] = cyc / ms
+    fn()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    es = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    spin_ms = 5.0 + 0.5 * reps
+    es.record(stream)
+    torch.cuda._sleep(int(spin_ms * _SPIN["cycles_per_ms"]))
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    host_ms = (time.perf_counter() - t0) * 1e3
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1), host_ms < es.elapsed_time(e0)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +233,9 @@ def main():
                     help="force the launch shape 'cols,tsteps,seg_rows' (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration for rocprofv3)")
+    ap.add_argument("--only-extras", default="", metavar="NAMES",
+                    help="run only these comma-separated extras and print them (profiling "
+                         "runs; no main metric)")
     ap.add_argument("--train-only", type=int, default=0, metavar="N",
                     help="only run N training steps of the differentiable 16 x 512^2, K = 20 "
                          "solve (profiling runs)")
@@ -241,6 +276,13 @@ def main():
     noisy, _ = wmc_synth.c2(side=side)
     f = torch.from_numpy(noisy).to(dev)           # (1, side, side)
     lam = torch.tensor([1.0], device=dev)
+    if args.only_extras:
+        only = set(args.only_extras.split(","))
+        unknown = only - set(EXTRA_NAMES)
+        if unknown:
+            sys.exit(f"unknown extras {sorted(unknown)}; known: {', '.join(EXTRA_NAMES)}")
+        print(json.dumps(extras(torch, wmc, wmc_synth, f, lam, stream, side, only)), flush=True)
+        return
 
     if args.tuning:
         c_, t_, r_ = (int(v) for v in args.tuning.split(","))
@@ -296,7 +338,47 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def extras(torch, wmc, wmc_synth, f, lam, stream, side):
+EXTRA_NAMES = ("copy_ceiling", "step_T1_4096", "step_T1_8192", "compute_4096", "fd_4096",
+               "step_T1_4096_cold", "c4_train_step", "volume_256cubed", "layer_k8_16x512",
+               "batched_c3")
+
+
+def extras(torch, wmc, wmc_synth, f, lam, stream, side, only=None):
+    ex = {}
+
+    def want(name):
+        return only is None or name in only
+    if want("copy_ceiling"):
+        ex.update(_copy_ceiling(torch, f, stream))
+    if want("step_T1_4096") or want("step_T1_8192"):
+        ex.update(_steps_t1(torch, wmc, f, lam, stream, side, want))
+    if want("compute_4096"):
+        ms, hid = timed_device(lambda: wmc.compute(f), 20, stream, torch)
+        ms /= 20
+        ex["compute_4096"] = {"gpx_per_s": round(side * side / (ms * 1e-3) / 1e9, 1),
+                              "gbs": round(8 * side * side / (ms * 1e-3) / 1e9, 1),
+                              "host_hidden": hid}
+    if want("fd_4096"):
+        # conventional finite-difference comparator on the same image (8 B/px)
+        ms, hid = timed_device(lambda: wmc.fd_compute(f), 20, stream, torch)
+        ms /= 20
+        ex["fd_4096"] = {"gpx_per_s": round(side * side / (ms * 1e-3) / 1e9, 1),
+                         "gbs": round(8 * side * side / (ms * 1e-3) / 1e9, 1),
+                         "host_hidden": hid}
+    if want("step_T1_4096_cold"):
+        ex.update(_step_cold(torch, f, lam, stream, side))
+    if want("c4_train_step"):
+        ex.update(_train(torch, wmc, wmc_synth, f, stream))
+    if want("volume_256cubed"):
+        ex.update(_volume(torch, wmc, f, stream))
+    if want("layer_k8_16x512"):
+        ex.update(_layer(torch, wmc, wmc_synth, f, stream))
+    if want("batched_c3"):
+        ex.update(_batched(torch, wmc, wmc_synth, f, stream))
+    return ex
+
+
+def _copy_ceiling(torch, f, stream):
     ex = {}
     # device copy ceiling: 1 GiB read + 1 GiB written
     a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=f.device).fill_(1.0)
@@ -306,6 +388,11 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side):
     ex["copy_ceiling"] = {"gbs": round(2 * a.numel() * 4 / (ms * 1e-3) / 1e9, 1),
                           "note": "torch copy of 1 GiB (read + write), the practical HBM ceiling"}
     del a, b
+    return ex
+
+
+def _steps_t1(torch, wmc, f, lam, stream, side, want):
+    ex = {}
     # plain single-update kernel (one launch per iteration, graph-replayed); the
     # launch shape is picked from a few candidates, best reported
     reps = 50
@@ -322,22 +409,25 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side):
                 best = (gbs, t1)
         return best
 
-    gbs, t1 = t1_gbs(f, side, reps, [(2, 14), (2, 16), (2, 28), (2, 32), (4, 8), (4, 23), (4, 32)])
-    ex["step_T1_4096"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                          "gpx_per_s": round(gbs / BYTES_PER_PX_PASS, 2), "tuning": t1,
-                          "note": "warm: the 192 MiB working set fits the 256 MB Infinity Cache"}
-    # 8192^2 control, larger than the Infinity Cache
-    g = torch.rand((1, 8192, 8192), device=f.device)
-    gbs, t1 = t1_gbs(g, 8192, 20, [(4, 4), (4, 8), (2, 4), (2, 14), (4, 12)])
-    ex["step_T1_8192"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                          "tuning": t1}
-    del g
-    # operator alone (read U, write H)
-    h = wmc.compute(f)
-    ms = timed(lambda: wmc.compute(f), 20, stream, torch) / 20
-    ex["compute_4096"] = {"gpx_per_s": round(side * side / (ms * 1e-3) / 1e9, 1),
-                          "gbs_incl_launch": round(8 * side * side / (ms * 1e-3) / 1e9, 1)}
-    del h
+    if want("step_T1_4096"):
+        gbs, t1 = t1_gbs(f, side, reps,
+                         [(2, 14), (2, 16), (2, 28), (2, 32), (4, 8), (4, 23), (4, 32)])
+        ex["step_T1_4096"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "gpx_per_s": round(gbs / BYTES_PER_PX_PASS, 2), "tuning": t1,
+                              "note": "warm: the 192 MiB working set fits the 256 MB Infinity "
+                                      "Cache"}
+    if want("step_T1_8192"):
+        # 8192^2 control, larger than the Infinity Cache
+        g = torch.rand((1, 8192, 8192), device=f.device)
+        gbs, t1 = t1_gbs(g, 8192, 20, [(4, 4), (4, 8), (2, 4), (2, 14), (4, 12)])
+        ex["step_T1_8192"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "tuning": t1}
+        del g
+    return ex
+
+
+def _step_cold(torch, f, lam, stream, side):
+    ex = {}
     # cold single update: four independent 4096^2 problems (768 MiB, three
     # times the Infinity Cache) updated round-robin, so every launch finds its
     # operands evicted; wmc_step launches enqueued back to back through the ABI
@@ -358,6 +448,11 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side):
                                "us_per_launch": round(ms * 1e3, 2),
                                "note": "wmc_step, 4 problems round-robin (768 MiB > Infinity Cache)"}
     del us, fs, outs
+    return ex
+
+
+def _train(torch, wmc, wmc_synth, f, stream):
+    ex = {}
     # differentiable solve (16 x 512 x 512, K = 20, checkpoint every 5): one
     # training step = fused forward with checkpoints + hand-written adjoint
     pxs = 16 * 512 * 512 * 20
@@ -374,29 +469,51 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side):
                     "note": "backward = segment recompute (none at period 1) + adjoint steps "
                             "+ lam reduction"}
         del x
+    return ex
+
+
+def _volume(torch, wmc, f, stream):
+    ex = {}
     # 3-D extension: one 256^3 volume, operator and data-term Jacobi steps
     vol = torch.rand((256, 256, 256), device=f.device)
-    h3 = wmc.compute3(vol)
-    ms_c3 = timed(lambda: wmc.compute3(vol), 10, stream, torch) / 10
-    wmc.solve3(vol, 1.0, 10)
-    ms_s3 = timed(lambda: wmc.solve3(vol, 1.0, 10), 3, stream, torch) / 3
+    ms_c3, hid_c = timed_device(lambda: wmc.compute3(vol), 10, stream, torch)
+    ms_s3, hid_s = timed_device(lambda: wmc.solve3(vol, 1.0, 10), 3, stream, torch)
+    ms_c3 /= 10
+    ms_s3 /= 3
     nv = vol.numel()
     ex["volume_256cubed"] = {"compute_gvox_s": round(nv / (ms_c3 * 1e-3) / 1e9, 1),
                              "solve_gvox_iter_s": round(nv * 10 / (ms_s3 * 1e-3) / 1e9, 1),
+                             "host_hidden": hid_c and hid_s,
                              "note": "18 half windows, one sweep per launch"}
-    del vol, h3
+    del vol
+    return ex
+
+
+def _layer(torch, wmc, wmc_synth, f, stream):
+    ex = {}
     # learnable half-window layer, 8 kernels, on the 16 x 512^2 batch
     xw = torch.from_numpy(wmc_synth.c4()[0][:, 0]).to(f.device)
     kw = wmc.nn.printed_kernels(device=f.device)
     out_l, sel_l = wmc.layer_forward(xw, kw)
     gl = torch.randn_like(xw)
-    ms_lf = timed(lambda: wmc.layer_forward(xw, kw), 10, stream, torch) / 10
-    ms_lb = timed(lambda: wmc.layer_backward(xw, kw, sel_l, gl), 10, stream, torch) / 10
+    reps = 20
+    ms_lf, h1 = timed_device(lambda: wmc.layer_forward(xw, kw), reps, stream, torch)
+    ms_lb, h2 = timed_device(lambda: wmc.layer_backward(xw, kw, sel_l, gl), reps, stream, torch)
+    ms_lu, h3 = timed_device(lambda: wmc.layer_backward(xw, kw, sel_l, gl, need_w=False), reps,
+                             stream, torch)
+    ms_lf, ms_lb, ms_lu = ms_lf / reps, ms_lb / reps, ms_lu / reps
     npx = xw.numel()
     ex["layer_k8_16x512"] = {"forward_gpx_s": round(npx / (ms_lf * 1e-3) / 1e9, 1),
                              "backward_gpx_s": round(npx / (ms_lb * 1e-3) / 1e9, 1),
-                             "ms_forward": round(ms_lf, 4), "ms_backward": round(ms_lb, 4)}
+                             "backward_input_grad_only_gpx_s": round(npx / (ms_lu * 1e-3) / 1e9, 1),
+                             "ms_forward": round(ms_lf, 4), "ms_backward": round(ms_lb, 4),
+                             "host_hidden": h1 and h2 and h3}
     del xw, out_l, sel_l, gl
+    return ex
+
+
+def _batched(torch, wmc, wmc_synth, f, stream):
+    ex = {}
     # uneven batch: 64 images x 3 channels, sides U{128..2048}, 100 iterations
     sizes = wmc_synth.c3_sizes()
     imgs = []

@@ -162,8 +162,9 @@ size_t wmc_batched_workspace(const wmc_image* imgs, int n_imgs);
  * wmc_solve_batched -- wmc_solve for many images of different sizes at once:
  * every channel of every image gets `iters` updates (each image with its own
  * lam[lam_index], channels independent, Sec. 5.4).  All tiles of all images
- * form one work list consumed by a persistent launch per fused block of
- * sweeps; the launch sequence is captured once into a hipGraph and replayed.
+ * form one work list, covered by one launch (one wave per item) per fused
+ * block of sweeps; the launch sequence is captured once into a hipGraph and
+ * replayed.
  * imgs: HOST array of n_imgs descriptors (device pointers inside).  Outputs
  * must not overlap any input or each other.  tune: NULL -> autotuned.
  * ------------------------------------------------------------------------- */

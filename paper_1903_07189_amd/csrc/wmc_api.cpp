@@ -217,7 +217,7 @@ std::vector<int> candidate_rows(int64_t planes, int64_t h, int64_t w, int C, int
 }
 
 // ---------------------------------------------------------------------------
-// cached launch plans: device-side work tables, counters and hipGraphs
+// cached launch plans: device-side work tables and hipGraphs
 // ---------------------------------------------------------------------------
 struct PlanEntry {
     hipGraphExec_t exec = nullptr;
@@ -406,9 +406,12 @@ int64_t img_extent(const BatchImg& b) { return (b.channels - 1) * b.ps + (b.h - 
 
 // Work table for one launch depth T: descriptors with strip/segment counts and
 // item bases.  Returns the number of work items.
+// Descriptor table of a batched launch and, if `owner` is given, the image of
+// every work item.  Returns the number of work items.
 int64_t build_table(const std::vector<BatchImg>& imgs, int C, int T, int R,
-                    std::vector<ImageDesc>& tab) {
+                    std::vector<ImageDesc>& tab, std::vector<int32_t>* owner = nullptr) {
     tab.clear();
+    if (owner) owner->clear();
     int64_t base = 0;
     for (const BatchImg& b : imgs) {
         ImageDesc d{};
@@ -428,7 +431,9 @@ int64_t build_table(const std::vector<BatchImg>& imgs, int C, int T, int R,
         d.nseg = seg_count((int)b.h, R);
         d.vec = vec_cols({b.src, b.f, b.out, b.tmp}, b.ld, b.channels > 1 ? b.ps : 0) >= C ? 1 : 0;
         d.item_base = base;
-        base += (int64_t)d.channels * d.nseg * d.nstrip;
+        const int64_t n = (int64_t)d.channels * d.nseg * d.nstrip;
+        base += n;
+        if (owner) owner->insert(owner->end(), (size_t)n, (int32_t)tab.size());
         tab.push_back(d);
     }
     return base;
@@ -453,30 +458,18 @@ std::vector<Launch> batch_schedule(int iters, int T) {
     return out;
 }
 
-// Persistent grid for (C, T, mode).
-int persistent_blocks(int dev, int C, int T, int mode, int64_t items) {
-    int per_cu = stream_blocks_per_cu(C, T, mode);
-    if (per_cu <= 0) per_cu = 1;
-    int64_t g = (int64_t)num_cu(dev) * per_cu;
-    const int64_t need = (items + 3) / 4;
-    if (g > need) g = need;
-    return (int)std::max<int64_t>(1, g);
-}
-
 // Enqueues (does not capture) a batched solve with explicit (C, T, R).
-// tables[T'] must hold device copies of the work tables for each depth used.
+// dtab[T'] / owner[T'] hold device copies of the work tables for each depth
+// used.
 int enqueue_batched(const std::vector<Launch>& sched, const std::map<int, ImageDesc*>& dtab,
-                    const std::map<int, int64_t>& items, int nimg, int C, int R, int mode,
-                    const float* lam, float dt, uint32_t* counters, int dev, hipStream_t st) {
-    hipError_t e = launch_fill_u32(counters, (int64_t)sched.size(), 0u, st);
-    if (e != hipSuccess) return hip_fail(e, "counter reset");
+                    const std::map<int, int32_t*>& owner, const std::map<int, int64_t>& items,
+                    int C, int R, int mode, const float* lam, float dt, hipStream_t st) {
     for (size_t l = 0; l < sched.size(); ++l) {
         const Launch& L = sched[l];
         LaunchArgs a{lam, dt, L.src_sel, L.dst_sel, R};
-        const int64_t n = items.at(L.T);
-        const int grid = persistent_blocks(dev, C, L.T, mode, n);
-        e = launch_stream_batched(C, L.T, mode, dtab.at(L.T), nimg, n, a, counters + l, grid, st);
-        if (e != hipSuccess) return hip_fail(e, "launch of the persistent kernel");
+        const hipError_t e = launch_stream_batched(C, L.T, mode, dtab.at(L.T), owner.at(L.T),
+                                                   items.at(L.T), a, st);
+        if (e != hipSuccess) return hip_fail(e, "launch of the batched kernel");
     }
     return WMC_OK;
 }
@@ -484,9 +477,32 @@ int enqueue_batched(const std::vector<Launch>& sched, const std::map<int, ImageD
 // Device-side work tables of one batched plan.
 struct BatchTables {
     std::map<int, ImageDesc*> dtab;  // per launch depth
+    std::map<int, int32_t*> owner;   // image of each work item, per launch depth
     std::map<int, int64_t> items;
-    uint32_t* counters = nullptr;
 };
+
+// Uploads the work tables of depth T into `t` (memory owned by `e`).
+int upload_tables(PlanEntry& e, BatchTables& t, const std::vector<BatchImg>& imgs, int C, int T,
+                  int R) {
+    std::vector<ImageDesc> tab;
+    std::vector<int32_t> own;
+    const int64_t n = build_table(imgs, C, T, R, tab, &own);
+    void* p = nullptr;
+    int rc = device_alloc(e, sizeof(ImageDesc) * tab.size(), &p);
+    if (rc) return rc;
+    WMC_HIP(hipMemcpy(p, tab.data(), sizeof(ImageDesc) * tab.size(), hipMemcpyHostToDevice),
+            "hipMemcpy (work table)");
+    void* q = nullptr;
+    rc = device_alloc(e, sizeof(int32_t) * std::max<size_t>(1, own.size()), &q);
+    if (rc) return rc;
+    if (!own.empty())
+        WMC_HIP(hipMemcpy(q, own.data(), sizeof(int32_t) * own.size(), hipMemcpyHostToDevice),
+                "hipMemcpy (item owners)");
+    t.dtab[T] = static_cast<ImageDesc*>(p);
+    t.owner[T] = static_cast<int32_t*>(q);
+    t.items[T] = n;
+    return WMC_OK;
+}
 
 // Full batched solve with a fixed tuning.
 int batched_run(const std::vector<BatchImg>& imgs, const float* lam, int iters, float dt,
@@ -506,27 +522,15 @@ int batched_run(const std::vector<BatchImg>& imgs, const float* lam, int iters, 
         auto t = std::make_shared<BatchTables>();
         for (const Launch& L : sched) {
             if (t->dtab.count(L.T)) continue;
-            std::vector<ImageDesc> tab;
-            const int64_t n = build_table(imgs, C, L.T, R, tab);
-            void* p = nullptr;
-            int rc = device_alloc(e, sizeof(ImageDesc) * tab.size(), &p);
+            const int rc = upload_tables(e, *t, imgs, C, L.T, R);
             if (rc) return rc;
-            WMC_HIP(hipMemcpy(p, tab.data(), sizeof(ImageDesc) * tab.size(), hipMemcpyHostToDevice),
-                    "hipMemcpy (work table)");
-            t->dtab[L.T] = static_cast<ImageDesc*>(p);
-            t->items[L.T] = n;
         }
-        void* c = nullptr;
-        int rc = device_alloc(e, sizeof(uint32_t) * std::max<size_t>(1, sched.size()), &c);
-        if (rc) return rc;
-        t->counters = static_cast<uint32_t*>(c);
         e.data = t;
         return WMC_OK;
     };
     auto enqueue = [&](hipStream_t s, PlanEntry& e) -> int {
         const BatchTables& t = *static_cast<const BatchTables*>(e.data.get());
-        return enqueue_batched(sched, t.dtab, t.items, (int)imgs.size(), C, R, mode, lam, dt,
-                               t.counters, dev, s);
+        return enqueue_batched(sched, t.dtab, t.owner, t.items, C, R, mode, lam, dt, s);
     };
     return run_plan(key, dev, st, use_graph, prepare, enqueue);
 }
@@ -755,7 +759,7 @@ std::string batch_tune_key(int dev, const std::vector<BatchImg>& imgs, int mode)
     }
     std::sort(ws.begin(), ws.end());
     std::ostringstream k;
-    k << arch_name(dev) << "|batch|" << (mode == kModeData ? "data" : "flow") << "|px" << ilog2_ceil(px)
+    k << arch_name(dev) << "|batch2|" << (mode == kModeData ? "data" : "flow") << "|px" << ilog2_ceil(px)
       << "|wmed" << ilog2_ceil(ws[ws.size() / 2]) << "|imgs" << ilog2_ceil((int64_t)imgs.size());
     return k.str();
 }
@@ -769,8 +773,6 @@ int tune_batch(int dev, const std::vector<BatchImg>& imgs, const float* lam, flo
         // one launch of T sweeps reading the inputs and writing the workspace
         auto run = [&](int C, int T, int R, hipStream_t ss) {
             std::vector<Launch> one{{T, 0, 2}};
-            std::vector<ImageDesc> tab;
-            const int64_t n = build_table(imgs, C, T, R, tab);
             std::string key = "tune|";
             key_add(key, C);
             key_add(key, T);
@@ -780,37 +782,47 @@ int tune_batch(int dev, const std::vector<BatchImg>& imgs, const float* lam, flo
             for (const BatchImg& b : imgs) key_add(key, b);
             auto prepare = [&](PlanEntry& e) -> int {
                 auto tb = std::make_shared<BatchTables>();
-                void* p = nullptr;
-                int rc = device_alloc(e, sizeof(ImageDesc) * tab.size(), &p);
+                const int rc = upload_tables(e, *tb, imgs, C, T, R);
                 if (rc) return rc;
-                WMC_HIP(hipMemcpy(p, tab.data(), sizeof(ImageDesc) * tab.size(),
-                                  hipMemcpyHostToDevice),
-                        "hipMemcpy (work table)");
-                tb->dtab[T] = static_cast<ImageDesc*>(p);
-                tb->items[T] = n;
-                void* c = nullptr;
-                rc = device_alloc(e, sizeof(uint32_t), &c);
-                if (rc) return rc;
-                tb->counters = static_cast<uint32_t*>(c);
                 e.data = tb;
                 return WMC_OK;
             };
             auto enqueue = [&](hipStream_t s2, PlanEntry& e) -> int {
                 const BatchTables& tb = *static_cast<const BatchTables*>(e.data.get());
-                return enqueue_batched(one, tb.dtab, tb.items, (int)imgs.size(), C, R, mode, lam,
-                                       dt, tb.counters, dev, s2);
+                return enqueue_batched(one, tb.dtab, tb.owner, tb.items, C, R, mode, lam, dt, s2);
             };
             return run_plan(key, dev, ss, false, prepare, enqueue);
         };
-        // the persistent batched kernel pulls items from a counter: no round
-        // quantisation, plain row counts
+        // plain row counts, and near 16, 32 and 64 the one whose item count
+        // best fills whole rounds of the device's resident waves (one wave
+        // per item, as in the single-image launch)
         auto rows = [&](int C, int T) {
-            (void)C;
             std::vector<int> out;
-            for (int R : {8, 16, 32, 64, 128}) {
-                if (R < 2 * T && R < hmax) continue;
-                if (R > 2 * hmax && R != 8) continue;
-                out.push_back(R);
+            auto add = [&](int R) {
+                if (R < 2 * T && R < hmax) return;
+                if (R > 2 * hmax && R != 8) return;
+                if (std::find(out.begin(), out.end(), R) == out.end()) out.push_back(R);
+            };
+            for (int R : {8, 16, 32, 64, 128}) add(R);
+            int per_cu = stream_blocks_per_cu(C, T, mode);
+            const int64_t slots = (int64_t)num_cu(dev) * std::max(1, per_cu) * 4;
+            std::vector<int64_t> strips;
+            for (const BatchImg& b : imgs) strips.push_back((int64_t)b.channels * strip_count((int)b.w, C, T));
+            for (int R0 : {16, 32, 64}) {
+                int bestR = 0;
+                double best = 1e30;
+                for (int R = std::max(2 * T, R0 * 3 / 4); R <= R0 * 5 / 4; ++R) {
+                    int64_t items = 0;
+                    for (size_t i = 0; i < imgs.size(); ++i)
+                        items += strips[i] * seg_count((int)imgs[i].h, R);
+                    const double rounds = (double)items / (double)slots;
+                    const double loss = std::ceil(rounds) / rounds;
+                    if (loss <= best) {
+                        best = loss;
+                        bestR = R;
+                    }
+                }
+                if (bestR) add(bestR);
             }
             return out;
         };

@@ -109,10 +109,14 @@ __device__ __forceinline__ Odd parts(float ta, float ts, float tq, float ms, flo
     o.E2 = ts - bs;
     const float B = __builtin_fmaf(2.0f, ms, ts + bs);
     o.A = __builtin_fmaf(-16.0f, mc, B);
-    o.E1 = __builtin_fmaf(2.0f, mq, tq + bq);
+    // E1, E5 and E6 share 2 q_m + q_b and 2 q_m + q_t: ten operations for
+    // the five parts instead of eleven
+    const float yb = __builtin_fmaf(2.0f, mq, bq);
+    const float yt = __builtin_fmaf(2.0f, mq, tq);
     const float da = ta - ba;
-    o.E5 = __builtin_fmaf(2.0f, mq, da + bq);
-    o.E6 = __builtin_fmaf(-2.0f, mq, da - tq);
+    o.E1 = tq + yb;
+    o.E5 = da + yb;
+    o.E6 = da - yt;
     return o;
 }
 

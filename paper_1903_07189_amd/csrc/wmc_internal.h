@@ -88,9 +88,10 @@ enum { kModeCompute = 0, kModeData = 1, kModeFlow = 2, kModeL1 = 3 };
 bool stream_variant_exists(int C, int T, int mode, bool argmin);
 hipError_t launch_stream_single(int C, int T, int mode, bool argmin, const ImageDesc& d,
                                 const LaunchArgs& a, hipStream_t st);
-hipError_t launch_stream_batched(int C, int T, int mode, const ImageDesc* dtable, int nimg,
-                                 int64_t total_items, const LaunchArgs& a, uint32_t* counter,
-                                 int grid_blocks, hipStream_t st);
+// One flat launch over the items of many images; owner[i] = image of item i.
+hipError_t launch_stream_batched(int C, int T, int mode, const ImageDesc* dtable,
+                                 const int32_t* owner, int64_t total_items, const LaunchArgs& a,
+                                 hipStream_t st);
 int stream_blocks_per_cu(int C, int T, int mode);
 int stream_single_blocks_per_cu(int C, int T, int mode, bool argmin);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);

@@ -341,32 +341,26 @@ __global__ __launch_bounds__(kBlock) void k_stream_single(ImageDesc d, LaunchArg
                             ring + ((MODE == kData || MODE == kL1) ? wv * (T + 1) * 64 * C : 0));
 }
 
-// Persistent variant: a fixed grid of waves pulls work items of all images
-// from a global counter (one counter per launch, zeroed by a fill kernel).
+// Batched variant: one flat launch over the work items of many images (each
+// image's items contiguous, in the order channel, segment, strip).  owner[i]
+// is the image of item i, so a wave finds its descriptor with two scalar
+// loads.  Items are equal-sized strips, so the hardware's dispatch of one
+// wave per item balances an uneven batch as well as a work queue would,
+// without a device-wide atomic per item (the 8 XCDs share no L2, so such an
+// atomic goes to memory and serialises every wave of the device on one
+// address).
 template <int C, int T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_stream_batched(const ImageDesc* __restrict__ tbl,
-                                                           int nimg, int64_t total,
-                                                           LaunchArgs a,
-                                                           uint32_t* __restrict__ counter) {
+                                                           const int32_t* __restrict__ owner,
+                                                           int64_t total, LaunchArgs a) {
     __shared__ float ring[ring_floats<C, T, MODE>()];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    float* myring = ring + (MODE == kData ? wv * (T + 1) * 64 * C : 0);
-    while (true) {
-        uint32_t got = 0;
-        if (lane == 0) got = atomicAdd(counter, 1u);
-        const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane((int)got);
-        if (item >= total) break;
-        // binary search: last image whose item_base <= item
-        int lo = 0, hi = nimg - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tbl[mid].item_base <= item) lo = mid;
-            else hi = mid - 1;
-        }
-        const ImageDesc d = tbl[lo];
-        process<C, T, MODE, false>(d, item - d.item_base, a, myring);
-    }
+    const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
+    if (item >= total) return;
+    const int img = __builtin_amdgcn_readfirstlane(owner[item]);
+    const ImageDesc d = tbl[img];
+    process<C, T, MODE, false>(d, item - d.item_base, a,
+                               ring + (MODE == kData ? wv * (T + 1) * 64 * C : 0));
 }
 
 __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
@@ -415,7 +409,7 @@ __global__ void k_selftest(int* flags) {
 // host side
 // ---------------------------------------------------------------------------
 using SingleFn = void (*)(ImageDesc, LaunchArgs);
-using BatchedFn = void (*)(const ImageDesc*, int, int64_t, LaunchArgs, uint32_t*);
+using BatchedFn = void (*)(const ImageDesc*, const int32_t*, int64_t, LaunchArgs);
 
 template <int C, int T, int MODE, bool AM>
 static SingleFn single_ptr() { return k_stream_single<C, T, MODE, AM>; }
@@ -521,13 +515,16 @@ int stream_blocks_per_cu(int C, int T, int mode) {
     return nb;
 }
 
-hipError_t launch_stream_batched(int C, int T, int mode, const ImageDesc* dtable, int nimg,
-                                 int64_t total_items, const LaunchArgs& a, uint32_t* counter,
-                                 int grid_blocks, hipStream_t st) {
+hipError_t launch_stream_batched(int C, int T, int mode, const ImageDesc* dtable,
+                                 const int32_t* owner, int64_t total_items, const LaunchArgs& a,
+                                 hipStream_t st) {
     BatchedFn fn = batched_table(C, T, mode);
-    if (!fn || grid_blocks <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(fn, dim3((unsigned)grid_blocks), dim3(kBlock), 0, st, dtable, nimg,
-                       total_items, a, counter);
+    if (!fn) return hipErrorInvalidValue;
+    const int64_t blocks = (total_items + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, st, dtable, owner, total_items,
+                       a);
     return hipGetLastError();
 }
 

@@ -469,8 +469,8 @@ def _images(fs, u0s, outs, lam_index):
 
 
 def solve_batched(fs, lam, iters: int, dt: float = 0.0, u0s=None, tuning=None):
-    """Solves many (C, H, W) images of different sizes in one persistent,
-    graph-replayed launch sequence.  lam: one value per image (tensor or list)."""
+    """Solves many (C, H, W) images of different sizes with one launch per
+    fused block of sweeps over the work items of all images, graph-replayed.  lam: one value per image (tensor or list)."""
     fs = [None if f is None else _planes(f).contiguous() for f in fs]
     u0s = [None] * len(fs) if u0s is None else [None if u is None else _planes(u).contiguous()
                                                  for u in u0s]

@@ -1,4 +1,4 @@
-"""Uneven-size batched solve (persistent launch, graph replay, autotuned
+"""Uneven-size batched solve (one launch over all images, graph replay, autotuned
 tiles) against per-image solves and, at full size, against the oracle on
 sampled pixels."""
 import numpy as np
