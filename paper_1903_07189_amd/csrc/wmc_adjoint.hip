@@ -415,23 +415,41 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_stream(AdjArgs A) {
 }
 
 // g_lam[p] += the step partial sums of plane p, steps from the last slot to
-// the first, each a fixed-order sum over the plane's work items.
+// the first, each a fixed-order sum over the plane's work items (per thread
+// in item order, then a fixed tree over the 256 threads).  Up to eight steps
+// are summed side by side, so their loads are in flight together and their
+// trees share barriers; the additions and their order are those of one step
+// at a time.
 __global__ __launch_bounds__(256) void k_lam_reduce(const float* __restrict__ part, int steps,
                                                     int64_t total, int64_t per_plane,
                                                     float* __restrict__ g_lam) {
+    constexpr int kSide = 8;
     const int p = blockIdx.x;
-    __shared__ float red[256];
-    for (int t = steps - 1; t >= 0; --t) {
-        const float* q = part + (int64_t)t * total + (int64_t)p * per_plane;
-        float s = 0.0f;
-        for (int64_t i = threadIdx.x; i < per_plane; i += 256) s += q[i];
-        red[threadIdx.x] = s;
+    __shared__ float red[kSide][256];
+    for (int t_hi = steps - 1; t_hi >= 0; t_hi -= kSide) {
+        const int nb = t_hi + 1 < kSide ? t_hi + 1 : kSide;  // steps t_hi, t_hi-1, ...
+#pragma unroll
+        for (int b = 0; b < kSide; ++b) {
+            float s = 0.0f;
+            if (b < nb) {
+                const float* q = part + (int64_t)(t_hi - b) * total + (int64_t)p * per_plane;
+                for (int64_t i = threadIdx.x; i < per_plane; i += 256) s += q[i];
+            }
+            red[b][threadIdx.x] = s;
+        }
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            if ((int)threadIdx.x < w) {
+#pragma unroll
+                for (int b = 0; b < kSide; ++b) red[b][threadIdx.x] += red[b][threadIdx.x + w];
+            }
             __syncthreads();
         }
-        if (threadIdx.x == 0) g_lam[p] += red[0];
+        if (threadIdx.x == 0) {
+            float acc = g_lam[p];
+            for (int b = 0; b < nb; ++b) acc += red[b][0];
+            g_lam[p] = acc;
+        }
         __syncthreads();
     }
 }

@@ -1615,7 +1615,6 @@ int wmc_fd_compute(const float* u, float* hw, float eps, wmc_shape s, void* stre
     const int64_t ext = extent_elems(s);
     if (overlaps(range_of(u, ext, 4), range_of(hw, ext, 4)))
         return fail(WMC_EINVAL, "wmc_fd_compute: output overlaps input");
-    if (s.h > 65535 * 4 || s.n > 65535) return fail(WMC_EINVAL, "wmc_fd_compute: image too tall");
     int dev;
     rc = check_device(&dev);
     if (rc) return rc;
@@ -1631,7 +1630,6 @@ int wmc_fd_flow(const float* u0, float* u_out, int iters, float dt, float eps, v
     if (!u0 || !u_out) return fail(WMC_EINVAL, "wmc_fd_flow: null pointer");
     if (iters < 0 || !std::isfinite(dt) || !(eps >= 0.0f) || !std::isfinite(eps))
         return fail(WMC_EINVAL, "wmc_fd_flow: bad iters, dt or eps");
-    if (s.h > 65535 * 4 || s.n > 65535) return fail(WMC_EINVAL, "wmc_fd_flow: image too tall");
     const int64_t ext = extent_elems(s);
     if (iters >= 2 && (!ws || ws_bytes < wmc_solve_workspace(s)))
         return fail(WMC_ENOMEM, "wmc_fd_flow: workspace smaller than wmc_solve_workspace()");

@@ -337,8 +337,19 @@ __global__ __launch_bounds__(256) void k_layer_wreduce(const float* __restrict__
     const int chunk = k / KC, kl = k - chunk * KC;
     const float* base = part + (int64_t)chunk * items * (9 * KC) + kl * 9 + t;
     __shared__ float red[256];
+    // each thread adds items threadIdx.x, +256, +512, ... in that order; the
+    // loads of eight of them are issued before the adds
+    const int64_t stride = 9 * KC;
     float s = 0.0f;
-    for (int64_t i = threadIdx.x; i < items; i += 256) s += base[i * (9 * KC)];
+    int64_t i = threadIdx.x;
+    for (; i + 7 * 256 < items; i += 8 * 256) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = base[(i + j * 256) * stride];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; i < items; i += 256) s += base[i * stride];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {

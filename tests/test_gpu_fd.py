@@ -43,7 +43,8 @@ def to_gpu(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0")
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (6, 1), (5, 9), (70, 133), (257, 300)])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (6, 1), (5, 9), (3, 124), (4, 125), (70, 133),
+                                   (130, 248), (257, 300), (1031, 40)])
 def test_fd_compute_parity(wmc, shape):
     U = wmc_synth.random_unit(*shape, seed=sum(shape))
     g = wmc.fd_compute(to_gpu(U)).cpu().numpy()
