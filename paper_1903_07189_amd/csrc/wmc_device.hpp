@@ -67,6 +67,16 @@ __device__ __forceinline__ float from_upper_lane(float old, float src) {
                                                       0x130, 0xF, 0xF, false));
 }
 
+// Lane L receives `src` of lane L-1 (L+1); the edge lane receives 0.  With
+// no old value to preserve, the compiler can fold these shifts into the
+// arithmetic that consumes them (DPP source operands).
+__device__ __forceinline__ float from_lower_lane_or_zero(float src) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(src), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float from_upper_lane_or_zero(float src) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(src), 0x130, 0xF, 0xF, true));
+}
+
 // Per-row quantities of C consecutive columns held by one lane; d is the
 // dual variable of the l1 iteration (unused by the other modes).
 template <int C>
@@ -88,6 +98,24 @@ __device__ __forceinline__ void make_row(const float (&m)[C], const bool (&last)
         float rr = (e == C - 1) ? rgt : m[e + 1];
         if (RCLAMP) rr = last[e] ? m[e] : rr;
         const float a = __builtin_fmaf(2.0f, m[e], l);
+        r.a[e] = a;
+        r.s[e] = a + rr;
+        r.q[e] = l - rr;
+        r.c[e] = m[e];
+    }
+}
+
+// make_row for a strip whose wave-edge lanes (0 and 63) are halo lanes whose
+// results are never stored: their missing neighbour may be zero.  Same
+// values as make_row<C, false> on every other lane (2m is exact, so l + 2m
+// rounds as fma(2, m, l)).
+template <int C>
+__device__ __forceinline__ void make_row_inner(const float (&m)[C], RowQ<C>& r) {
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+        const float l = (e == 0) ? from_lower_lane_or_zero(m[C - 1]) : m[e - 1];
+        const float rr = (e == C - 1) ? from_upper_lane_or_zero(m[0]) : m[e + 1];
+        const float a = (e == 0) ? l + 2.0f * m[e] : __builtin_fmaf(2.0f, m[e], l);
         r.a[e] = a;
         r.s[e] = a + rr;
         r.q[e] = l - rr;

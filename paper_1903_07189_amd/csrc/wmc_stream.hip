@@ -78,12 +78,26 @@ struct Item {
 };
 
 
+// Kinds of strip (work-item column ranges):
+//   kGeneric   an image narrower than one strip, or a border strip whose
+//              rows cannot be moved with vector accesses: clamped scalar
+//              loads, the element holding the last image column uses itself
+//              as its right neighbour, wave-edge lanes keep their own values;
+//   kBorder    the first strip (starting at column 0) or the last one
+//              (right-aligned, ending at column W-1): lane 0 of the first and
+//              lane 63 of the last keep their own values as their missing
+//              neighbour, which is the replicate border at every sweep;
+//   kInterior  lanes 0 and 63 are halo lanes whose results are never stored,
+//              so their missing neighbours are zero (make_row_inner, whose
+//              lane shifts fold into the arithmetic).
+// In a launch whose items all run at once the slowest item sets the time, so
+// the border strips get their own vector-access variant.
+enum StripKind : int { kGeneric = 0, kBorder = 1, kInterior = 2 };
+
 // Runs one work item: rows of T sweeps pipelined in registers (see top of
-// file).  RCL: this strip holds the last image column (replicate clamp inside
-// the wave, scalar clamped loads).  VEC: rows are 4C-byte aligned and the
-// strip lies inside the image, so every lane moves its C columns with one
-// vector access.
-template <int C, int T, int MODE, bool AM, bool RCL, bool VEC>
+// file).  VEC: rows are 4C-byte aligned and the strip lies inside the image,
+// so every lane moves its C columns with one vector access.
+template <int C, int T, int MODE, bool AM, int KIND, bool VEC>
 __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring) {
     constexpr bool L1 = (MODE == kL1);
     constexpr bool DATA = (MODE == kData) || L1;  // modes that read f
@@ -91,7 +105,7 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
     const int lane = threadIdx.x & 63;
     const int xb = it.x0 + C * lane;
     const int H = it.H, W = it.W;
-    static_assert(!(RCL && VEC), "the border strip uses clamped scalar loads");
+    static_assert(!(KIND == kGeneric && VEC), "the generic strip uses clamped scalar loads");
 
     bool last[C], ok[C];
     int xc[C];  // clamped columns for scalar loads
@@ -228,7 +242,9 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
             }
             put_ring(n, pf[P]);
             if (n + 3 < hi0) load(pf[P], n + 3);
-            make_row<C, RCL>(m, last, win[0][P]);
+            if constexpr (KIND == kGeneric) make_row<C, true>(m, last, win[0][P]);
+            else if constexpr (KIND == kBorder) make_row<C, false>(m, last, win[0][P]);
+            else make_row_inner<C>(m, win[0][P]);
             if constexpr (L1) {
 #pragma unroll
                 for (int e = 0; e < C; ++e) win[0][P].d[e] = dm[e];
@@ -249,7 +265,9 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
                 sweep_row(win[k - 1][PT], win[k - 1][PM], win[k - 1][P], rho, v, idx, dv);
                 if (k < T) {
                     RowQ<C>(&lv)[3] = win[k < T ? k : 0];
-                    make_row<C, RCL>(v, last, lv[P]);
+                    if constexpr (KIND == kGeneric) make_row<C, true>(v, last, lv[P]);
+                    else if constexpr (KIND == kBorder) make_row<C, false>(v, last, lv[P]);
+                    else make_row_inner<C>(v, lv[P]);
                     if constexpr (L1) {
 #pragma unroll
                         for (int e = 0; e < C; ++e) lv[P].d[e] = dv[e];
@@ -308,19 +326,29 @@ __device__ __forceinline__ void process(const ImageDesc& d, int64_t local, const
     it.ld = d.ld;
     it.H = d.H;
     it.W = d.W;
-    const int width = 64 * C, halo = halo_cols(C, T);
-    it.x0 = strip * (width - 2 * halo);
-    it.ox0 = strip == 0 ? 0 : it.x0 + halo;
-    it.ox1 = strip == d.nstrip - 1 ? d.W : it.x0 + width - halo;
+    const int width = 64 * C, halo = halo_cols(C, T), step = width - 2 * halo;
+    const bool first = strip == 0, lastS = strip == d.nstrip - 1;
+    // the last of several strips is right-aligned: it ends at column W-1
+    // (W <= (nstrip-1)*step + width, so its own columns keep their halo)
+    it.x0 = (lastS && !first) ? d.W - width : strip * step;
+    it.ox0 = first ? 0 : strip * step + halo;
+    it.ox1 = lastS ? d.W : strip * step + width - halo;
     it.y0 = seg * a.R;
     it.y1 = it.y0 + a.R < d.H ? it.y0 + a.R : d.H;
     it.vec = d.vec != 0;
     const float lam = a.lam ? a.lam[d.lam_index + ch * d.lam_stride] : 0.0f;
     if constexpr (MODE == kL1) it.k = make_coef_l1(lam, a.dt, a.alpha);
     else it.k = make_coef(lam, a.dt, MODE == kData);
-    if (strip == d.nstrip - 1) run_item<C, T, MODE, AM, true, false>(it, ring);
-    else if (it.vec) run_item<C, T, MODE, AM, false, true>(it, ring);
-    else run_item<C, T, MODE, AM, false, false>(it, ring);
+    if (first || lastS) {
+        if (!(first && lastS) && it.vec && it.x0 % C == 0)
+            run_item<C, T, MODE, AM, kBorder, true>(it, ring);
+        else
+            run_item<C, T, MODE, AM, kGeneric, false>(it, ring);
+    } else if (it.vec) {
+        run_item<C, T, MODE, AM, kInterior, true>(it, ring);
+    } else {
+        run_item<C, T, MODE, AM, kInterior, false>(it, ring);
+    }
 }
 
 template <int C, int T, int MODE>
@@ -391,8 +419,9 @@ __global__ void k_copy_planes(const float* __restrict__ src, float* __restrict__
         dst[p * ps + y * ld + x] = src[p * ps + y * ld + x];
 }
 
-// Lane-shift self test: flags[0] = 1 iff from_lower_lane / from_upper_lane
-// move data as the kernels assume, for every lane of a wave.
+// Lane-shift self test: flags[w] = 1 iff the lane shifts of wmc_device.hpp
+// (with kept and with zero edge values) move data as the kernels assume, for
+// every lane of wave w.
 __global__ void k_selftest(int* flags) {
     const int lane = threadIdx.x & 63;
     const float me = (float)(lane + 1);
@@ -400,7 +429,11 @@ __global__ void k_selftest(int* flags) {
     const float up = from_upper_lane(-me, me);
     const float want_lo = lane == 0 ? -me : (float)lane;
     const float want_up = lane == 63 ? -me : (float)(lane + 2);
-    const bool good = (lo == want_lo) && (up == want_up);
+    const float loz = from_lower_lane_or_zero(me);
+    const float upz = from_upper_lane_or_zero(me);
+    const float want_loz = lane == 0 ? 0.0f : (float)lane;
+    const float want_upz = lane == 63 ? 0.0f : (float)(lane + 2);
+    const bool good = (lo == want_lo) && (up == want_up) && (loz == want_loz) && (upz == want_upz);
     const unsigned long long ballot = __ballot(good);
     if (lane == 0) flags[threadIdx.x >> 6] = (ballot == ~0ull) ? 1 : 0;
 }
