@@ -542,16 +542,22 @@ struct SLaunch {
     int T;
     const float* src;
     float* dst;
+    float* traj[3];  // checkpoints reached after sweeps 1..T-1 of this launch (or null)
 };
 
+// Launch sequence of a single plane-set solve.  Checkpoint states that fall
+// inside a fused launch are stored by the trajectory variant when it exists
+// for T (2..kTrajMaxT); otherwise launches end at every checkpoint.
 std::vector<SLaunch> solve_schedule(int iters, int T, int ckpt_every, const float* src0,
                                     float* u_out, float* ws, float* ckpt, int64_t set_stride) {
     std::vector<int> depth;
     std::vector<int> end_t;
     int t = 0;
+    const bool traj = ckpt && ckpt_every > 0 && T >= 2 && T <= kTrajMaxT;
     while (t < iters) {
         int stop = iters;
-        if (ckpt && ckpt_every > 0) stop = std::min(iters, (t / ckpt_every + 1) * ckpt_every);
+        if (ckpt && ckpt_every > 0 && !traj)
+            stop = std::min(iters, (t / ckpt_every + 1) * ckpt_every);
         std::vector<int> parts;
         split_run(stop - t, T, parts);
         for (int d : parts) {
@@ -571,13 +577,21 @@ std::vector<SLaunch> solve_schedule(int iters, int T, int ckpt_every, const floa
             dst = (out[l + 1].dst == u_out) ? ws : u_out;
         out[l].dst = dst;
         out[l].T = depth[l];
+        for (int k = 0; k < 3; ++k) out[l].traj[k] = nullptr;
+        if (traj) {
+            const int t0 = end_t[l] - depth[l];
+            for (int k = 1; k < depth[l]; ++k)
+                if ((t0 + k) % ckpt_every == 0)
+                    out[l].traj[k - 1] = ckpt + (int64_t)((t0 + k) / ckpt_every) * set_stride;
+        }
     }
     for (int l = 0; l < L; ++l) out[l].src = l == 0 ? src0 : out[l - 1].dst;
     return out;
 }
 
 int enqueue_single(const wmc_shape& s, const float* src, const float* f, float* dst,
-                   const float* lam, float dt, int C, int T, int R, hipStream_t st) {
+                   const float* lam, float dt, int C, int T, int R, hipStream_t st,
+                   float* const* traj = nullptr) {
     const int mode = f ? kModeData : kModeFlow;
     const bool vec = vec_cols({src, f, dst}, s.ld, s.n > 1 ? s.ps : 0) >= C;
     ImageDesc d{};
@@ -596,7 +610,13 @@ int enqueue_single(const wmc_shape& s, const float* src, const float* f, float* 
     d.nseg = seg_count((int)s.h, R);
     d.vec = vec ? 1 : 0;
     LaunchArgs a{lam, dt, 0, 1, R};
-    const hipError_t e = launch_stream_single(C, T, mode, false, d, a, st);
+    bool any = false;
+    for (int k = 0; traj && k < 3; ++k) {
+        a.traj[k] = k < T - 1 ? traj[k] : nullptr;
+        any = any || a.traj[k];
+    }
+    const hipError_t e = any ? launch_stream_traj(C, T, mode, d, a, st)
+                             : launch_stream_single(C, T, mode, false, d, a, st);
     if (e != hipSuccess) return hip_fail(e, "launch of the streaming kernel");
     return WMC_OK;
 }
@@ -1004,7 +1024,12 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
         rc = resolve_tuning(tune, auto_t, &t, &graph);
     }
     if (rc) return rc;
-    (void)mode;
+    // checkpoints closer together than T would cut the fused launches short:
+    // use the deepest launch that stores states inside itself instead
+    if (nck && ckpt_every < t.T && t.T > kTrajMaxT) {
+        t.T = kTrajMaxT;
+        t.R = default_rows(s.n, s.h, s.w, t.C, t.T, dev, mode);
+    }
     const std::vector<SLaunch> sched =
         solve_schedule(iters, t.T, ckpt ? ckpt_every : 0, src0, u_out, static_cast<float*>(ws),
                        nck ? ckpt : nullptr, stride);
@@ -1014,7 +1039,7 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
             if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
         }
         for (const SLaunch& L : sched) {
-            const int r = enqueue_single(s, L.src, f, L.dst, lam, dt, t.C, L.T, t.R, ss);
+            const int r = enqueue_single(s, L.src, f, L.dst, lam, dt, t.C, L.T, t.R, ss, L.traj);
             if (r) return r;
         }
         return WMC_OK;
@@ -1305,6 +1330,11 @@ int wmc_autotune(const wmc_image* imgs, int n_imgs, int iters, wmc_tuning* out, 
     return WMC_OK;
 }
 
+// dL/dlam partial sums are kept for up to this many steps before they are
+// reduced (at least one checkpoint segment, at least 8 steps when there are
+// that many): the reductions add the steps in descending order either way.
+int lam_slots(int iters, int c) { return std::max(c, std::min(8, std::max(iters, 1))); }
+
 size_t wmc_backward_workspace(wmc_shape s, int iters, int ckpt_every) {
     if (check_shape(s) || iters < 0 || ckpt_every < 1) return 0;
     const size_t set = (size_t)set_stride_elems(s) * sizeof(float);
@@ -1315,7 +1345,7 @@ size_t wmc_backward_workspace(wmc_shape s, int iters, int ckpt_every) {
     // the column width with the most work items
     int64_t items = 0;
     for (int C : {1, 2, 4}) items = std::max(items, adj_items(s.n, s.h, s.w, C));
-    const size_t part = (size_t)c * (size_t)items * sizeof(float);
+    const size_t part = (size_t)lam_slots(iters, c) * (size_t)items * sizeof(float);
     return states + grads + (part + 255) / 256 * 256;
 }
 
@@ -1355,7 +1385,10 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     const bool data = f != nullptr;
     // recompute launches: plain single sweeps, paired columns when aligned
     const int C1 = std::min(2, vec_cols({ckpt, states, f, u0}, s.ld, s.n > 1 ? s.ps : 0));
-    const int R1 = default_rows(s.n, s.h, s.w, C1, 1, dev, data ? kModeData : kModeFlow);
+    const int mode1 = data ? kModeData : kModeFlow;
+    int R1[kTrajMaxT + 1] = {0};
+    for (int T = 1; T <= kTrajMaxT; ++T) R1[T] = default_rows(s.n, s.h, s.w, C1, T, dev, mode1);
+    const int G = lam_slots(iters, c);
     // adjoint launches (WMC_ADJ_COLS=2|4 selects wider lanes)
     const char* env_cols = std::getenv("WMC_ADJ_COLS");
     int CA = 1;
@@ -1392,30 +1425,43 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     float* gcur = gA;
     float* gnext = gB;
     const int nseg = (int)wmc_num_checkpoints(iters, ckpt_every);
+    int used = 0;  // dL/dlam slots holding steps not yet reduced (slot G-1 first)
     for (int sg = nseg - 1; sg >= 0; --sg) {
         const int t0 = sg * ckpt_every;
         const int t1 = std::min(t0 + ckpt_every, iters);
         std::vector<const float*> st_ptr(t1 - t0);
         st_ptr[0] = ckpt + (int64_t)sg * set;
-        for (int t = t0 + 1; t < t1; ++t) {
-            float* dst = states + (int64_t)(t - t0 - 1) * set;
-            rc = enqueue_single(s, st_ptr[t - t0 - 1], f, dst, lam, dt, C1, 1, R1, st);
+        // recompute the segment's states: fused launches of up to kTrajMaxT
+        // sweeps that store every state (bitwise the same as single sweeps)
+        for (int j = 0; j < t1 - t0 - 1;) {
+            const int T = std::min(kTrajMaxT, t1 - t0 - 1 - j);
+            float* traj[3] = {nullptr, nullptr, nullptr};
+            for (int k = 1; k < T; ++k) traj[k - 1] = states + (int64_t)(j + k - 1) * set;
+            float* dst = states + (int64_t)(j + T - 1) * set;
+            rc = enqueue_single(s, st_ptr[j], f, dst, lam, dt, C1, T, R1[T], st, traj);
             if (rc) return rc;
-            st_ptr[t - t0] = dst;
+            for (int k = 1; k <= T; ++k) st_ptr[j + k] = states + (int64_t)(j + k - 1) * set;
+            j += T;
         }
         for (int t = t1 - 1; t >= t0; --t) {
             a.u = st_ptr[t - t0];
             a.g = gcur;
             a.g_prev = gnext;
-            a.slot = t - t0;
+            a.slot = G - 1 - used;
             e = launch_adjoint_step(a, st);
             if (e != hipSuccess) return hip_fail(e, "adjoint launch");
             std::swap(gcur, gnext);
+            if (a.part && ++used == G) {
+                e = launch_lambda_reduce(part, G, items, items / s.n, s.n, g_lam, st);
+                if (e != hipSuccess) return hip_fail(e, "lambda reduction");
+                used = 0;
+            }
         }
-        if (a.part) {
-            e = launch_lambda_reduce(part, t1 - t0, items, items / s.n, s.n, g_lam, st);
-            if (e != hipSuccess) return hip_fail(e, "lambda reduction");
-        }
+    }
+    if (a.part && used > 0) {
+        e = launch_lambda_reduce(part + (int64_t)(G - used) * items, used, items, items / s.n, s.n,
+                                 g_lam, st);
+        if (e != hipSuccess) return hip_fail(e, "lambda reduction");
     }
     if (g_u0) {
         e = launch_copy_planes(gcur, g_u0, s.n, s.h, s.w, s.ld, s.ps, st);

@@ -80,12 +80,22 @@ struct LaunchArgs {
     int32_t dst_sel;   // 1: bufA, 2: bufB
     int32_t R;         // output rows per work item
     float alpha;       // l1 mode: dual bound
+    // trajectory launches (k_stream_traj): the state after sweep k (1 <= k < T)
+    // is also stored to traj[k-1] (a plane set with the layout of the image),
+    // or not at all where traj[k-1] is null
+    float* traj[3];
 };
+
+constexpr int kTrajMaxT = 4;  // trajectory launches exist for T = 2, 3, 4
 
 enum { kModeCompute = 0, kModeData = 1, kModeFlow = 2, kModeL1 = 3 };
 
 // Host-side launchers (wmc_stream.hip).  Return a hipError_t.
 bool stream_variant_exists(int C, int T, int mode, bool argmin);
+// A launch of T sweeps that also stores the states after sweeps 1..T-1 where
+// a.traj[k-1] is set (data and flow modes, T <= kTrajMaxT).
+hipError_t launch_stream_traj(int C, int T, int mode, const ImageDesc& d, const LaunchArgs& a,
+                              hipStream_t st);
 hipError_t launch_stream_single(int C, int T, int mode, bool argmin, const ImageDesc& d,
                                 const LaunchArgs& a, hipStream_t st);
 // One flat launch over the items of many images; owner[i] = image of item i.

@@ -75,6 +75,7 @@ struct Item {
     int y0, y1;
     bool vec;
     Coef k;
+    float* traj[3];  // trajectory stores (plane offset applied), see LaunchArgs
 };
 
 
@@ -96,8 +97,9 @@ enum StripKind : int { kGeneric = 0, kBorder = 1, kInterior = 2 };
 
 // Runs one work item: rows of T sweeps pipelined in registers (see top of
 // file).  VEC: rows are 4C-byte aligned and the strip lies inside the image,
-// so every lane moves its C columns with one vector access.
-template <int C, int T, int MODE, bool AM, int KIND, bool VEC>
+// so every lane moves its C columns with one vector access.  TRAJ: the owned
+// rows of sweeps 1..T-1 are also stored where it.traj[k-1] is set.
+template <int C, int T, int MODE, bool AM, int KIND, bool VEC, bool TRAJ>
 __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring) {
     constexpr bool L1 = (MODE == kL1);
     constexpr bool DATA = (MODE == kData) || L1;  // modes that read f
@@ -164,6 +166,23 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
                 p.u[e] = ld_at<float>(up, (uint32_t)xc[e]);
                 if (needf) p.f[e] = ld_at<float>(fp, (uint32_t)xc[e]);
             }
+        }
+    };
+
+    // stores an owned row of intermediate sweep k (trajectory launches)
+    auto store_traj = [&](float* base, int rho, const float (&v)[C]) {
+        if (rho < it.y0 || rho >= it.y1) return;  // wave-uniform
+        float* dp = base + (int64_t)rho * it.ld;
+        if constexpr (VEC) {
+            if (all_ok) {
+                if constexpr (C == 4) st_at<float4>(dp, (uint32_t)xb, make_float4(v[0], v[1], v[2], v[3]));
+                else if constexpr (C == 2) st_at<float2>(dp, (uint32_t)xb, make_float2(v[0], v[1]));
+                else st_at<float>(dp, (uint32_t)xb, v[0]);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < C; ++e)
+                if (ok[e]) st_at<float>(dp, (uint32_t)(xb + e), v[e]);
         }
     };
 
@@ -264,6 +283,9 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
                 int idx[C];
                 sweep_row(win[k - 1][PT], win[k - 1][PM], win[k - 1][P], rho, v, idx, dv);
                 if (k < T) {
+                    if constexpr (TRAJ) {
+                        if (it.traj[k - 1]) store_traj(it.traj[k - 1], rho, v);
+                    }
                     RowQ<C>(&lv)[3] = win[k < T ? k : 0];
                     if constexpr (KIND == kGeneric) make_row<C, true>(v, last, lv[P]);
                     else if constexpr (KIND == kBorder) make_row<C, false>(v, last, lv[P]);
@@ -297,7 +319,7 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
 }
 
 // Resolves work item `item` of image d into an Item and runs it.
-template <int C, int T, int MODE, bool AM>
+template <int C, int T, int MODE, bool AM, bool TRAJ = false>
 __device__ __forceinline__ void process(const ImageDesc& d, int64_t local, const LaunchArgs& a,
                                         float* ring) {
     const int64_t per_plane = (int64_t)d.nseg * d.nstrip;
@@ -336,18 +358,20 @@ __device__ __forceinline__ void process(const ImageDesc& d, int64_t local, const
     it.y0 = seg * a.R;
     it.y1 = it.y0 + a.R < d.H ? it.y0 + a.R : d.H;
     it.vec = d.vec != 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) it.traj[k] = (TRAJ && a.traj[k]) ? a.traj[k] + poff : nullptr;
     const float lam = a.lam ? a.lam[d.lam_index + ch * d.lam_stride] : 0.0f;
     if constexpr (MODE == kL1) it.k = make_coef_l1(lam, a.dt, a.alpha);
     else it.k = make_coef(lam, a.dt, MODE == kData);
     if (first || lastS) {
         if (!(first && lastS) && it.vec && it.x0 % C == 0)
-            run_item<C, T, MODE, AM, kBorder, true>(it, ring);
+            run_item<C, T, MODE, AM, kBorder, true, TRAJ>(it, ring);
         else
-            run_item<C, T, MODE, AM, kGeneric, false>(it, ring);
+            run_item<C, T, MODE, AM, kGeneric, false, TRAJ>(it, ring);
     } else if (it.vec) {
-        run_item<C, T, MODE, AM, kInterior, true>(it, ring);
+        run_item<C, T, MODE, AM, kInterior, true, TRAJ>(it, ring);
     } else {
-        run_item<C, T, MODE, AM, kInterior, false>(it, ring);
+        run_item<C, T, MODE, AM, kInterior, false, TRAJ>(it, ring);
     }
 }
 
@@ -367,6 +391,18 @@ __global__ __launch_bounds__(kBlock) void k_stream_single(ImageDesc d, LaunchArg
     if (item >= total) return;
     process<C, T, MODE, AM>(d, item, a,
                             ring + ((MODE == kData || MODE == kL1) ? wv * (T + 1) * 64 * C : 0));
+}
+
+// Trajectory variant of k_stream_single: also stores the states after the
+// intermediate sweeps (checkpoints that fall inside a fused launch).
+template <int C, int T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stream_traj(ImageDesc d, LaunchArgs a) {
+    __shared__ float ring[ring_floats<C, T, MODE>()];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t total = (int64_t)d.channels * d.nseg * d.nstrip;
+    const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
+    if (item >= total) return;
+    process<C, T, MODE, false, true>(d, item, a, ring + (MODE == kData ? wv * (T + 1) * 64 * C : 0));
 }
 
 // Batched variant: one flat launch over the work items of many images (each
@@ -510,6 +546,28 @@ static BatchedFn batched_table(int C, int T, int mode) {
                                              {WMC_T_LIST(WMC_B, 4, kFlow)}};
 #undef WMC_B
     return mode == kModeData ? data_tab[ci][ti] : flow_tab[ci][ti];
+}
+
+hipError_t launch_stream_traj(int C, int T, int mode, const ImageDesc& d, const LaunchArgs& a,
+                              hipStream_t st) {
+    const int ci = cindex(C);
+    if (ci < 0 || T < 2 || T > kTrajMaxT || (mode != kModeData && mode != kModeFlow))
+        return hipErrorInvalidValue;
+    static const SingleFn data_tab[3][3] = {
+        {k_stream_traj<1, 2, kData>, k_stream_traj<1, 3, kData>, k_stream_traj<1, 4, kData>},
+        {k_stream_traj<2, 2, kData>, k_stream_traj<2, 3, kData>, k_stream_traj<2, 4, kData>},
+        {k_stream_traj<4, 2, kData>, k_stream_traj<4, 3, kData>, k_stream_traj<4, 4, kData>}};
+    static const SingleFn flow_tab[3][3] = {
+        {k_stream_traj<1, 2, kFlow>, k_stream_traj<1, 3, kFlow>, k_stream_traj<1, 4, kFlow>},
+        {k_stream_traj<2, 2, kFlow>, k_stream_traj<2, 3, kFlow>, k_stream_traj<2, 4, kFlow>},
+        {k_stream_traj<4, 2, kFlow>, k_stream_traj<4, 3, kFlow>, k_stream_traj<4, 4, kFlow>}};
+    SingleFn fn = mode == kModeData ? data_tab[ci][T - 2] : flow_tab[ci][T - 2];
+    const int64_t total = (int64_t)d.channels * d.nseg * d.nstrip;
+    const int64_t blocks = (total + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, st, d, a);
+    return hipGetLastError();
 }
 
 bool stream_variant_exists(int C, int T, int mode, bool argmin) {

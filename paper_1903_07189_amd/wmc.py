@@ -535,19 +535,32 @@ def release():
     lib().wmc_release()
 
 
+# Keeping every state of the forward (checkpoint period 1) removes the
+# backward's recomputation; the fused forward stores them as it goes.  It
+# costs K plane sets of memory, so it is the default only up to this size.
+KEEP_ALL_STATES_BYTES = 2 << 30
+
+
+def default_ckpt_every(K: int, plane_set_bytes: int) -> int:
+    """1 (keep every state) when K states fit KEEP_ALL_STATES_BYTES, else
+    ceil(sqrt(K)) (about 2 sqrt(K) states in memory, one recomputation)."""
+    K = max(int(K), 1)
+    if K * int(plane_set_bytes) <= KEEP_ALL_STATES_BYTES:
+        return 1
+    return max(1, math.ceil(math.sqrt(K)))
+
+
 class WMCSolve(torch.autograd.Function):
     """U^K = solve(f, lam, K) as a differentiable layer: forward runs the fused
-    solver storing a checkpoint every ckpt_every steps (default ceil(sqrt(K))),
-    backward runs the hand-written adjoint, recomputing each segment from its
-    checkpoint.  Gradients flow to f (N, H, W) and to lam (N,).  (Keeping every
-    state, ckpt_every = 1, removes the recomputation but not the time: the
-    adjoint then reads states that are no longer in the Infinity Cache, and
-    the forward cannot fuse sweeps.)"""
+    solver storing a checkpoint every ckpt_every steps (default
+    default_ckpt_every), backward runs the hand-written adjoint, recomputing
+    each segment from its checkpoint.  Gradients flow to f (N, H, W) and to
+    lam (N,)."""
 
     @staticmethod
     def forward(ctx, f, lam, K: int, dt: float = 0.0, ckpt_every: int | None = None, tuning=None):
         K = int(K)
-        c = int(ckpt_every) if ckpt_every else max(1, math.ceil(math.sqrt(K)))
+        c = int(ckpt_every) if ckpt_every else default_ckpt_every(K, f.numel() * 4)
         lam_t = _lam_tensor(lam, _planes(f).shape[0], f.device)
         out, ck = solve(f.detach(), lam_t, K, dt=dt, ckpt_every=c, tuning=tuning)
         ctx.save_for_backward(f.detach(), lam_t, ck)

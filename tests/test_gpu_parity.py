@@ -220,6 +220,35 @@ def test_checkpoints_are_the_states(wmc):
     assert torch.equal(out, wmc.solve(f, 0.8, 13, tuning=tun))
 
 
+@pytest.mark.parametrize("cols,tsteps,every", [(1, 2, 1), (2, 3, 1), (2, 4, 1), (4, 3, 2),
+                                                (1, 4, 3), (2, 3, 5), (2, 4, 7), (2, 6, 4),
+                                                (1, 8, 1), (2, 6, 7)])
+@pytest.mark.parametrize("flow", [False, True])
+def test_checkpoints_inside_fused_launches(wmc, cols, tsteps, every, flow):
+    """Checkpoints that fall inside a fused launch (stored by the trajectory
+    variant, T <= 4; a deeper T with denser checkpoints runs T = 4 launches,
+    a deeper T with sparser ones ends its launches at the checkpoints) are
+    bitwise the states of single steps, on a ragged multi-strip shape."""
+    rng = np.random.default_rng(100 + 10 * cols + tsteps + every)
+    f = to_gpu(rng.uniform(0, 1, size=(2, 37, 150)))
+    tun = {"cols": cols, "tsteps": tsteps, "seg_rows": 9}
+    K = 17
+    if flow:
+        out, ck = wmc.solve(None, iters=K, dt=0.3, u0=f, ckpt_every=every, tuning=tun)
+    else:
+        out, ck = wmc.solve(f, 0.7, K, ckpt_every=every, tuning=tun)
+    assert ck.shape[0] == -(-K // every)
+    u = f.clone()
+    step1 = {"cols": cols, "tsteps": 1, "seg_rows": 9}
+    for t in range(K + 1):
+        if t % every == 0 and t < K:
+            assert torch.equal(ck[t // every], u), t
+        if t < K:
+            u = (wmc.solve(None, iters=1, dt=0.3, u0=u, tuning=step1) if flow
+                 else wmc.solve(f, 0.7, 1, u0=u, tuning=step1))
+    assert torch.equal(out, u)
+
+
 def test_default_tuning_path(wmc, monkeypatch, tmp_path):
     """The autotuned default (no tuning given) is bitwise the same result."""
     monkeypatch.setenv("WMC_TUNE_CACHE", str(tmp_path / "tune.json"))
