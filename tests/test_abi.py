@@ -189,3 +189,17 @@ def test_layer_and_fd_validation(wmc):
     assert L.wmc_fd_compute(P(4096), P(1 << 20), -1.0, S, None) == wmc.WMC_EINVAL
     assert L.wmc_fd_flow(P(4096), P(1 << 20), -1, 0.1, 1e-12, None, 0, S, None) == wmc.WMC_EINVAL
     assert L.wmc_fd_flow(P(4096), P(1 << 20), 5, 0.1, 1e-12, P(1 << 21), 8, S, None) == wmc.WMC_ENOMEM
+
+
+def test_default_checkpoint_period_policy():
+    """Every state is kept while K plane sets fit the budget, else ceil(sqrt(K))."""
+    from paper_1903_07189_amd import wmc as W
+    set_c4 = 16 * 512 * 512 * 4
+    assert W.default_ckpt_every(20, set_c4) == 1
+    assert W.default_ckpt_every(30, 32 * 256 * 256 * 4) == 1
+    big = 4096 * 4096 * 4
+    assert W.default_ckpt_every(200, big) == 15
+    assert W.default_ckpt_every(1, big) == 1
+    budget = W.KEEP_ALL_STATES_BYTES
+    assert W.default_ckpt_every(4, budget // 4) == 1
+    assert W.default_ckpt_every(4, budget // 4 + 1) == 2
