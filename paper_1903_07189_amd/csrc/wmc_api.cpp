@@ -168,8 +168,9 @@ void split_run(int len, int T, std::vector<int>& out) {
 // strips)), R = ceil(h / nseg) -- the smallest k whose R is at least
 // max(8, 4T) rows (segment overlap costs T rows per sweep depth).  slots =
 // resident waves of this kernel variant (occupancy API) times the CUs.
-int64_t resident_waves(int dev, int C, int T, int mode) {
-    int per_cu = stream_single_blocks_per_cu(C, T, mode, false);
+int64_t resident_waves(int dev, int C, int T, int mode, bool traj = false) {
+    int per_cu = traj ? stream_traj_blocks_per_cu(C, T, mode)
+                      : stream_single_blocks_per_cu(C, T, mode, false);
     if (per_cu <= 0) per_cu = 1;
     return (int64_t)num_cu(dev) * per_cu * 4;  // 4 waves per 256-thread block
 }
@@ -181,8 +182,9 @@ int rows_for_rounds(int64_t planes, int64_t h, int64_t w, int C, int T, int64_t 
     return (int)std::max<int64_t>(1, std::min<int64_t>(R, h));
 }
 
-int default_rows(int64_t planes, int64_t h, int64_t w, int C, int T, int dev, int mode) {
-    const int64_t slots = resident_waves(dev, C, T, mode);
+int default_rows(int64_t planes, int64_t h, int64_t w, int C, int T, int dev, int mode,
+                 bool traj = false) {
+    const int64_t slots = resident_waves(dev, C, T, mode, traj);
     const int64_t rmin = std::min<int64_t>(h, std::max<int64_t>(8, 4 * (int64_t)T));
     for (int k = 1; k <= 64; ++k) {
         const int R = rows_for_rounds(planes, h, w, C, T, slots, k);
@@ -1028,7 +1030,12 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
     // use the deepest launch that stores states inside itself instead
     if (nck && ckpt_every < t.T && t.T > kTrajMaxT) {
         t.T = kTrajMaxT;
-        t.R = default_rows(s.n, s.h, s.w, t.C, t.T, dev, mode);
+        t.R = default_rows(s.n, s.h, s.w, t.C, t.T, dev, mode, true);
+    } else if (nck && t.T >= 2 && t.T <= kTrajMaxT && !tuning_complete(tune) &&
+               stream_traj_blocks_per_cu(t.C, t.T, mode) !=
+                   stream_single_blocks_per_cu(t.C, t.T, mode, false)) {
+        // the trajectory variant holds fewer waves: fill its rounds instead
+        t.R = default_rows(s.n, s.h, s.w, t.C, t.T, dev, mode, true);
     }
     const std::vector<SLaunch> sched =
         solve_schedule(iters, t.T, ckpt ? ckpt_every : 0, src0, u_out, static_cast<float*>(ws),
@@ -1387,7 +1394,7 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     const int C1 = std::min(2, vec_cols({ckpt, states, f, u0}, s.ld, s.n > 1 ? s.ps : 0));
     const int mode1 = data ? kModeData : kModeFlow;
     int R1[kTrajMaxT + 1] = {0};
-    for (int T = 1; T <= kTrajMaxT; ++T) R1[T] = default_rows(s.n, s.h, s.w, C1, T, dev, mode1);
+    for (int T = 1; T <= kTrajMaxT; ++T) R1[T] = default_rows(s.n, s.h, s.w, C1, T, dev, mode1, T > 1);
     const int G = lam_slots(iters, c);
     // adjoint launches (WMC_ADJ_COLS=2|4 selects wider lanes)
     const char* env_cols = std::getenv("WMC_ADJ_COLS");

@@ -104,6 +104,7 @@ hipError_t launch_stream_batched(int C, int T, int mode, const ImageDesc* dtable
                                  hipStream_t st);
 int stream_blocks_per_cu(int C, int T, int mode);
 int stream_single_blocks_per_cu(int C, int T, int mode, bool argmin);
+int stream_traj_blocks_per_cu(int C, int T, int mode);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 hipError_t launch_copy_planes(const float* src, float* dst, int64_t n, int64_t h, int64_t w,

@@ -396,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_single(ImageDesc d, LaunchArg
 // Trajectory variant of k_stream_single: also stores the states after the
 // intermediate sweeps (checkpoints that fall inside a fused launch).
 template <int C, int T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_stream_traj(ImageDesc d, LaunchArgs a) {
+__global__ __launch_bounds__(kBlock, (C == 2 ? 3 : 1)) void k_stream_traj(ImageDesc d, LaunchArgs a) {
     __shared__ float ring[ring_floats<C, T, MODE>()];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t total = (int64_t)d.channels * d.nseg * d.nstrip;
@@ -568,6 +568,25 @@ hipError_t launch_stream_traj(int C, int T, int mode, const ImageDesc& d, const 
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(kBlock), 0, st, d, a);
     return hipGetLastError();
+}
+
+int stream_traj_blocks_per_cu(int C, int T, int mode) {
+    const int ci = cindex(C);
+    if (ci < 0 || T < 2 || T > kTrajMaxT || (mode != kModeData && mode != kModeFlow)) return 0;
+    static const SingleFn data_tab[3][3] = {
+        {k_stream_traj<1, 2, kData>, k_stream_traj<1, 3, kData>, k_stream_traj<1, 4, kData>},
+        {k_stream_traj<2, 2, kData>, k_stream_traj<2, 3, kData>, k_stream_traj<2, 4, kData>},
+        {k_stream_traj<4, 2, kData>, k_stream_traj<4, 3, kData>, k_stream_traj<4, 4, kData>}};
+    static const SingleFn flow_tab[3][3] = {
+        {k_stream_traj<1, 2, kFlow>, k_stream_traj<1, 3, kFlow>, k_stream_traj<1, 4, kFlow>},
+        {k_stream_traj<2, 2, kFlow>, k_stream_traj<2, 3, kFlow>, k_stream_traj<2, 4, kFlow>},
+        {k_stream_traj<4, 2, kFlow>, k_stream_traj<4, 3, kFlow>, k_stream_traj<4, 4, kFlow>}};
+    SingleFn fn = mode == kModeData ? data_tab[ci][T - 2] : flow_tab[ci][T - 2];
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn), kBlock,
+                                                     0) != hipSuccess)
+        return 0;
+    return nb;
 }
 
 bool stream_variant_exists(int C, int T, int mode, bool argmin) {
