@@ -1375,6 +1375,8 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     for (const void* p : {(const void*)g_f, (const void*)g_u0})
         if (p && (overlaps(range_of(p, ext, 4), rw) || overlaps(range_of(p, ext, 4), range_of(g_out, ext, 4))))
             return fail(WMC_EINVAL, "wmc_backward: outputs overlap the workspace or g_out");
+    if (g_f && g_u0 && overlaps(range_of(g_f, ext, 4), range_of(g_u0, ext, 4)))
+        return fail(WMC_EINVAL, "wmc_backward: g_f and g_u0 overlap");
     int dev;
     rc = check_device(&dev);
     if (rc) return rc;
@@ -1427,10 +1429,12 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
         e = launch_fill_f32(g_f, (s.n - 1) * s.ps + (s.h - 1) * s.ld + s.w, 0.0f, st);
         if (e != hipSuccess) return hip_fail(e, "fill");
     }
-    e = launch_copy_planes(g_out, gA, s.n, s.h, s.w, s.ld, s.ps, st);
-    if (e != hipSuccess) return hip_fail(e, "copy");
-    float* gcur = gA;
-    float* gnext = gB;
+    // the first adjoint step reads g_out itself; the steps then alternate
+    // between gA and gB, and the last one writes g_u0 when it is wanted
+    const float* gcur = g_out;
+    float* gbuf[2] = {gA, gB};
+    int gnext = 0;
+    int left = iters;
     const int nseg = (int)wmc_num_checkpoints(iters, ckpt_every);
     int used = 0;  // dL/dlam slots holding steps not yet reduced (slot G-1 first)
     for (int sg = nseg - 1; sg >= 0; --sg) {
@@ -1451,13 +1455,16 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
             j += T;
         }
         for (int t = t1 - 1; t >= t0; --t) {
+            float* dst = (left == 1 && g_u0) ? g_u0 : gbuf[gnext];
             a.u = st_ptr[t - t0];
             a.g = gcur;
-            a.g_prev = gnext;
+            a.g_prev = dst;
             a.slot = G - 1 - used;
             e = launch_adjoint_step(a, st);
             if (e != hipSuccess) return hip_fail(e, "adjoint launch");
-            std::swap(gcur, gnext);
+            if (dst == gbuf[gnext]) gnext ^= 1;
+            gcur = dst;
+            --left;
             if (a.part && ++used == G) {
                 e = launch_lambda_reduce(part, G, items, items / s.n, s.n, g_lam, st);
                 if (e != hipSuccess) return hip_fail(e, "lambda reduction");
@@ -1470,8 +1477,8 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
                                  g_lam, st);
         if (e != hipSuccess) return hip_fail(e, "lambda reduction");
     }
-    if (g_u0) {
-        e = launch_copy_planes(gcur, g_u0, s.n, s.h, s.w, s.ld, s.ps, st);
+    if (g_u0 && iters == 0) {
+        e = launch_copy_planes(g_out, g_u0, s.n, s.h, s.w, s.ld, s.ps, st);
         if (e != hipSuccess) return hip_fail(e, "copy");
     }
     if (data && g_f && !u0) {

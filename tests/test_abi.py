@@ -139,6 +139,12 @@ def test_backward_validation(wmc):
                           None, P(1 << 22), 1 << 16, S, None) == wmc.WMC_EINVAL  # no ckpt
     assert L.wmc_backward(P(4096), None, P(64), 5, 0.0, P(1 << 23), 2, P(1 << 20), P(1 << 21),
                           None, None, P(1 << 22), 8, S, None) == wmc.WMC_ENOMEM
+    need = L.wmc_backward_workspace(S, 5, 2)
+    # g_f and g_u0 must be distinct buffers (the last step writes g_u0, then
+    # dL/df adds it)
+    assert L.wmc_backward(P(4096), None, P(64), 5, 0.0, P(1 << 23), 2, P(1 << 20), P(1 << 21),
+                          P(1 << 21), None, P(1 << 24), need, S, None) == wmc.WMC_EINVAL
+    assert "overlap" in L.wmc_last_error().decode()
 
 
 def test_valid_call_without_device_reports_hip_error(wmc):
