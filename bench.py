@@ -338,7 +338,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-EXTRA_NAMES = ("copy_ceiling", "step_T1_4096", "step_T1_8192", "compute_4096", "fd_4096",
+EXTRA_NAMES = ("copy_ceiling", "step_T1_4096", "step_T1_8192", "compute_4096", "fd_4096", "l1_4096",
                "step_T1_4096_cold", "c4_train_step", "volume_256cubed", "layer_k8_16x512",
                "batched_c3")
 
@@ -365,6 +365,14 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side, only=None):
         ex["fd_4096"] = {"gpx_per_s": round(side * side / (ms * 1e-3) / 1e9, 1),
                          "gbs": round(8 * side * side / (ms * 1e-3) / 1e9, 1),
                          "host_hidden": hid}
+    if want("l1_4096"):
+        # l1-fidelity primal-dual solve on the same image, autotuned (20 B/px
+        # per launch: U, d, f in; U, d out)
+        wmc.solve_l1(f, 10.0, 0.05, 200)
+        ms = timed(lambda: wmc.solve_l1(f, 10.0, 0.05, 200), 3, stream, torch) / 3
+        ex["l1_4096"] = {"gpx_iter_s": round(side * side * 200 / (ms * 1e-3) / 1e9, 1),
+                         "ms": round(ms, 3), "lam": 10.0, "alpha": 0.05, "iters": 200,
+                         "note": "l1-fidelity primal-dual iteration, fused sweeps"}
     if want("step_T1_4096_cold"):
         ex.update(_step_cold(torch, f, lam, stream, side))
     if want("c4_train_step"):

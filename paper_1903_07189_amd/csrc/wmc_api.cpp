@@ -1338,9 +1338,10 @@ int wmc_autotune(const wmc_image* imgs, int n_imgs, int iters, wmc_tuning* out, 
 }
 
 // dL/dlam partial sums are kept for up to this many steps before they are
-// reduced (at least one checkpoint segment, at least 8 steps when there are
-// that many): the reductions add the steps in descending order either way.
-int lam_slots(int iters, int c) { return std::max(c, std::min(8, std::max(iters, 1))); }
+// reduced (at least one checkpoint segment, up to 64 steps: one float per
+// work item and step): the reductions add the steps in descending order
+// either way.
+int lam_slots(int iters, int c) { return std::max(c, std::min(64, std::max(iters, 1))); }
 
 size_t wmc_backward_workspace(wmc_shape s, int iters, int ckpt_every) {
     if (check_shape(s) || iters < 0 || ckpt_every < 1) return 0;
