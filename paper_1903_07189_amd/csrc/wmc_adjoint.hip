@@ -41,6 +41,8 @@
 // reproducible and independent of the checkpoint period.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "wmc_device.hpp"
 #include "wmc_internal.h"
 
@@ -69,8 +71,8 @@ __device__ __forceinline__ void zero_frow(FRow<C>& r) {
 // (halo columns, whose results are not used).
 template <int C>
 __device__ __forceinline__ void nbrs(const float (&x)[C], float (&l)[C], float (&r)[C]) {
-    const float lft = from_lower_lane(0.0f, x[C - 1]);
-    const float rgt = from_upper_lane(0.0f, x[0]);
+    const float lft = from_lower_lane_or_zero(x[C - 1]);
+    const float rgt = from_upper_lane_or_zero(x[0]);
 #pragma unroll
     for (int e = 0; e < C; ++e) {
         l[e] = (e == 0) ? lft : x[e - 1];
@@ -82,11 +84,13 @@ template <int C>
 __device__ __forceinline__ void make_frow(const float (&G)[C], const float (&W1)[C],
                                           const float (&W2)[C], const float (&W5)[C],
                                           const float (&W6)[C], FRow<C>& o) {
+    // l + 2x is written as l + (x + x) (2x is exact, so it rounds as
+    // fma(2, x, l)): additions accept a lane-shifted operand directly
     float l[C], r[C];
     nbrs(G, l, r);
 #pragma unroll
     for (int e = 0; e < C; ++e) {
-        o.gs[e] = __builtin_fmaf(2.0f, G[e], l[e]) + r[e];
+        o.gs[e] = (l[e] + (G[e] + G[e])) + r[e];
         o.gc[e] = G[e];
     }
     nbrs(W1, l, r);
@@ -94,17 +98,17 @@ __device__ __forceinline__ void make_frow(const float (&G)[C], const float (&W1)
     for (int e = 0; e < C; ++e) o.q1[e] = l[e] - r[e];
     nbrs(W2, l, r);
 #pragma unroll
-    for (int e = 0; e < C; ++e) o.s2[e] = __builtin_fmaf(2.0f, W2[e], l[e]) + r[e];
+    for (int e = 0; e < C; ++e) o.s2[e] = (l[e] + (W2[e] + W2[e])) + r[e];
     nbrs(W5, l, r);
 #pragma unroll
     for (int e = 0; e < C; ++e) {
-        o.a5[e] = __builtin_fmaf(2.0f, W5[e], l[e]);
+        o.a5[e] = l[e] + (W5[e] + W5[e]);
         o.q5[e] = l[e] - r[e];
     }
     nbrs(W6, l, r);
 #pragma unroll
     for (int e = 0; e < C; ++e) {
-        o.a6[e] = __builtin_fmaf(2.0f, W6[e], l[e]);
+        o.a6[e] = l[e] + (W6[e] + W6[e]);
         o.q6[e] = l[e] - r[e];
     }
 }
@@ -165,7 +169,6 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
         isR[e] = x == W - 1;
         xc[e] = x < 0 ? 0 : (x < W ? x : W - 1);
     }
-    const bool never[C] = {};
 
     float pu[3][C], pg[3][C], pfv[3][C], pgf[3][C];  // prefetch slots
     RowQ<C> uw[3];                                    // U row quantities, rows n-2..n
@@ -184,16 +187,22 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
 
     const int n0 = it.y0 - 2, nend = it.y1 + 2;
 
-    auto load = [&](float (&u)[C], float (&g)[C], float (&fv)[C], float (&gf)[C], int row) {
+    auto load = [&](float (&u)[C], float (&g)[C], float (&fv)[C], float (&gf)[C], int row,
+                    bool any_row) {
         const int rr = row < 0 ? 0 : (row < H ? row : H - 1);
         const float* up = it.u + (int64_t)rr * it.ld;
         const float* gp = it.g + (int64_t)rr * it.ld;
         const float* fp = DATA ? it.f + (int64_t)rr * it.ld : nullptr;
-        // dL/df is read-modify-written on owned rows only (wave-uniform test)
-        if (DATA && it.g_f && row >= it.y0 && row < it.y1) {
+        // dL/df is read-modify-written on owned rows and columns only; with
+        // any_row (steady steps) the row is loaded whether owned or not, at
+        // clamped columns, and the values of rows and columns that are not
+        // owned are never used
+        if (DATA && it.g_f && (any_row || (row >= it.y0 && row < it.y1))) {
             const float* qp = it.g_f + (int64_t)rr * it.ld;
 #pragma unroll
-            for (int e = 0; e < C; ++e) gf[e] = own[e] ? ld_at<float>(qp, (uint32_t)(xb + e)) : 0.0f;
+            for (int e = 0; e < C; ++e)
+                gf[e] = any_row ? ld_at<float>(qp, (uint32_t)xc[e])
+                                : (own[e] ? ld_at<float>(qp, (uint32_t)(xb + e)) : 0.0f);
         }
         if constexpr (VEC && C == 4) {
             const float4 a = ld_at<float4>(up, (uint32_t)xb);
@@ -243,8 +252,14 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
 
     int n = n0;
 
-    auto step = [&](auto phase_tag) {
+    // One row step.  ST ("steady"): a step whose every border and ownership
+    // test below is known to pass -- row n+3 is still to be prefetched, stage
+    // A's row n-1 and stage B's row n-2 are owned rows, neither is the first
+    // or last image row -- so that the step is straight-line code.  Steady and
+    // generic steps do the same arithmetic.
+    auto step = [&](auto phase_tag, auto steady_tag) {
         constexpr int P = decltype(phase_tag)::value;
+        constexpr bool ST = decltype(steady_tag)::value;
         constexpr int PM = (P + 2) % 3;  // row n-1
         constexpr int PT = (P + 1) % 3;  // row n-2 (and n+1 for the prefetch)
         // row n out of its prefetch slot, then refill the slot with row n+3
@@ -256,40 +271,42 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
             fr[P][e] = DATA ? pfv[P][e] : 0.0f;
             gfr[P][e] = DATA ? pgf[P][e] : 0.0f;
         }
-        if (n + 3 <= nend) load(pu[P], pg[P], pfv[P], pgf[P], n + 3);
-        make_row<C, false>(m, never, uw[P]);
+        if (ST || n + 3 <= nend) load(pu[P], pg[P], pfv[P], pgf[P], n + 3, ST);
+        // lanes 0 and 63 take zero for their missing neighbour: their
+        // selections only reach stencils of halo columns that are not stored
+        make_row_inner<C>(m, uw[P]);
 
         // stage A: fields of row rho = n-1 (zero outside the image)
         const int rho = n - 1;
-        if (rho >= it.y0 - 1) {
+        if (ST || rho >= it.y0 - 1) {
             float G[C], W1[C], W2[C], W5[C], W6[C];
-            if (rho >= 0 && rho < H) {
-                const bool owned_row = rho >= it.y0 && rho < it.y1;
+            if (ST || (rho >= 0 && rho < H)) {
+                const bool owned_row = ST || (rho >= it.y0 && rho < it.y1);
                 float* gfp = (DATA && it.g_f && owned_row) ? it.g_f + (int64_t)rho * it.ld : nullptr;
 #pragma unroll
                 for (int e = 0; e < C; ++e) {
                     const Odd o = parts(uw[PT].a[e], uw[PT].s[e], uw[PT].q[e], uw[PM].s[e],
                                         uw[PM].q[e], uw[PM].c[e], uw[P].a[e], uw[P].s[e],
                                         uw[P].q[e]);
-                    int idx;
-                    const float S = select_x12_idx(o, idx);
-                    const float gv = inimg[e] ? gr[PM][e] : 0.0f;
-                    const float sg = (idx & 2) ? -gv : gv;
-                    const int fam = idx & 5;
+                    Pick pk;
+                    const float S = select_x12_pick(o, pk);
+                    const float gv = (!EDGE || inimg[e]) ? gr[PM][e] : 0.0f;
+                    const float sg = in_mask(pk.neg) ? -gv : gv;
                     G[e] = gv;
-                    W1[e] = fam == 0 ? sg : 0.0f;
-                    W2[e] = fam == 1 ? sg : 0.0f;
-                    W5[e] = fam == 4 ? sg : 0.0f;
-                    W6[e] = fam == 5 ? sg : 0.0f;
+                    W1[e] = in_mask(~pk.half & ~pk.second) ? sg : 0.0f;
+                    W2[e] = in_mask(~pk.half & pk.second) ? sg : 0.0f;
+                    W5[e] = in_mask(pk.half & ~pk.second) ? sg : 0.0f;
+                    W6[e] = in_mask(pk.half & pk.second) ? sg : 0.0f;
                     if constexpr (DATA) {
-                        if (owned_row && own[e]) {
+                        if (owned_row) {
                             const float hd = to_hd(S);
                             float dudl = it.delta * hd;
                             if (it.dlam_default)
                                 dudl -= it.delta * it.delta * ((fr[PM][e] - uw[PM].c[e]) + it.lam * hd);
-                            contrib = __builtin_fmaf(gv, dudl, contrib);
-                            if (gfp) st_at<float>(gfp, (uint32_t)(xb + e),
-                                                  __builtin_fmaf(it.delta, gv, gfr[PM][e]));
+                            const float c1 = __builtin_fmaf(gv, dudl, contrib);
+                            contrib = own[e] ? c1 : contrib;
+                            if (gfp && own[e])
+                                st_at<float>(gfp, (uint32_t)(xb + e), __builtin_fmaf(it.delta, gv, gfr[PM][e]));
                         }
                     }
                 }
@@ -304,17 +321,17 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
 
         // stage B: row r = n-2
         const int r = n - 2;
-        const bool owned = r >= it.y0 && r < it.y1;
-        const bool top = r == -1 && it.y0 == 0;
-        const bool bot = r == H && it.y1 == H;
+        const bool owned = ST || (r >= it.y0 && r < it.y1);
+        const bool top = !ST && r == -1 && it.y0 == 0;
+        const bool bot = !ST && r == H && it.y1 == H;
         if (owned || top || bot) {
             float acc[C];
 #pragma unroll
             for (int e = 0; e < C; ++e) acc[e] = stencil(fw[P], fw[PT], fw[PM], e);
             if constexpr (EDGE) {
                 // column ring: virtual column -1 onto column 0, W onto W-1
-                const float lft = from_lower_lane(0.0f, acc[C - 1]);
-                const float rgt = from_upper_lane(0.0f, acc[0]);
+                const float lft = from_lower_lane_or_zero(acc[C - 1]);
+                const float rgt = from_upper_lane_or_zero(acc[0]);
                 float add[C];
 #pragma unroll
                 for (int e = 0; e < C; ++e) {
@@ -334,11 +351,11 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
                 for (int e = 0; e < C; ++e) acc[e] += pend[e];
                 store(H - 1, acc, pendg);
             } else {
-                if (r == 0) {
+                if (!ST && r == 0) {
 #pragma unroll
                     for (int e = 0; e < C; ++e) acc[e] += topfold[e];
                 }
-                if (r == H - 1) {
+                if (!ST && r == H - 1) {
 #pragma unroll
                     for (int e = 0; e < C; ++e) {
                         pend[e] = acc[e];
@@ -352,14 +369,43 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
     };
 
 #pragma unroll
-    for (int j = 0; j < 3; ++j) load(pu[j], pg[j], pfv[j], pgf[j], n0 + j);
+    for (int j = 0; j < 3; ++j) load(pu[j], pg[j], pfv[j], pgf[j], n0 + j, false);
 
+    // steady steps: n in [max(y0 + 2, 3), y1 - 1] (see `step`)
+    const int s_lo = it.y0 + 2 > 3 ? it.y0 + 2 : 3;
+    const int s_hi = it.y1 - 1;
+    using Gen = std::false_type;
+    using Std = std::true_type;
+    // groups of three steps: the register slot of a row is fixed by its
+    // position in the group
+    // generic groups up to the first steady step of phase 0, steady groups,
+    // then generic groups to the end
+    const int ns = s_lo + (3 - (s_lo - n0) % 3) % 3;
+    const int groups = s_hi >= ns + 2 ? (s_hi - ns + 1) / 3 : 0;
+    if (groups > 0) {
+        while (n < ns) {
+            step(APhase<0>{}, Gen{});
+            ++n;
+            step(APhase<1>{}, Gen{});
+            ++n;
+            step(APhase<2>{}, Gen{});
+            ++n;
+        }
+        for (int k = 0; k < groups; ++k) {
+            step(APhase<0>{}, Std{});
+            ++n;
+            step(APhase<1>{}, Std{});
+            ++n;
+            step(APhase<2>{}, Std{});
+            ++n;
+        }
+    }
     while (true) {
-        step(APhase<0>{});
+        step(APhase<0>{}, Gen{});
         if (++n > nend) break;
-        step(APhase<1>{});
+        step(APhase<1>{}, Gen{});
         if (++n > nend) break;
-        step(APhase<2>{});
+        step(APhase<2>{}, Gen{});
         if (++n > nend) break;
     }
 

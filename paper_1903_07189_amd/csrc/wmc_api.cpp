@@ -1417,6 +1417,12 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     a.ps = s.ps;
     a.C = CA;
     a.R = adj_rows(s.n, s.h, s.w, CA);
+    // WMC_ADJ_ROWS=R: rows per adjoint work item, at least the default (the
+    // workspace holds the lambda partials of the default item count)
+    if (const char* env_rows = std::getenv("WMC_ADJ_ROWS")) {
+        const int r = std::atoi(env_rows);
+        if (r > a.R && r <= 4096) a.R = r;
+    }
     a.nstrip = adj_strip_count((int)s.w, CA);
     a.nseg = seg_count((int)s.h, a.R);
     a.vec = vecA ? 1 : 0;

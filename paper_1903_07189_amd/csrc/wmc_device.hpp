@@ -180,6 +180,38 @@ __device__ __forceinline__ float select_x12_idx(const Odd& o, int& idx) {
     return r3 ? x1 : x0;
 }
 
+// Lane masks of the wave (bit L = lane L): a per-lane condition as a mask and
+// back.  Logic on masks runs as scalar instructions.
+__device__ __forceinline__ uint64_t lanes(bool c) { return __builtin_amdgcn_ballot_w64(c); }
+__device__ __forceinline__ bool in_mask(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// Same tournament, describing the winner by lane masks instead of an index:
+// `half` (S5..S8), `second` (the E2 / E6 member of its half) and `neg`
+// (S = A - E); winner index = 4 half + 2 neg + second.  Called with every
+// lane of the wave active.
+struct Pick {
+    uint64_t half, second, neg;
+};
+__device__ __forceinline__ float select_x12_pick(const Odd& o, Pick& p) {
+    const float s0 = o.A + o.E1, s1 = o.A + o.E2, s2 = o.A - o.E1, s3 = o.A - o.E2;
+    const float s4 = o.A + o.E5, s5 = o.A + o.E6, s6 = o.A - o.E5, s7 = o.A - o.E6;
+    const bool r0 = __builtin_fabsf(s1) < __builtin_fabsf(s0);
+    const bool r1 = __builtin_fabsf(s3) < __builtin_fabsf(s2);
+    const bool r2 = __builtin_fabsf(s5) < __builtin_fabsf(s4);
+    const bool r3 = __builtin_fabsf(s7) < __builtin_fabsf(s6);
+    const float w0 = r0 ? s1 : s0, w1 = r1 ? s3 : s2, w2 = r2 ? s5 : s4, w3 = r3 ? s7 : s6;
+    const bool q0 = __builtin_fabsf(w1) < __builtin_fabsf(w0);
+    const bool q1 = __builtin_fabsf(w3) < __builtin_fabsf(w2);
+    const float x0 = q0 ? w1 : w0, x1 = q1 ? w3 : w2;
+    const bool h = __builtin_fabsf(x1) < __builtin_fabsf(x0);
+    const uint64_t R0 = lanes(r0), R1 = lanes(r1), R2 = lanes(r2), R3 = lanes(r3);
+    const uint64_t Q0 = lanes(q0), Q1 = lanes(q1), Hm = lanes(h);
+    p.half = Hm;
+    p.neg = (Hm & Q1) | (~Hm & Q0);
+    p.second = (Hm & ((Q1 & R3) | (~Q1 & R2))) | (~Hm & ((Q0 & R1) | (~Q0 & R0)));
+    return h ? x1 : x0;
+}
+
 // Output modes of the streaming kernel.
 enum Mode : int { kCompute = 0, kData = 1, kFlow = 2, kL1 = 3 };
 
