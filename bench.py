@@ -228,7 +228,8 @@ def main():
     ap.add_argument("--side", type=int, default=4096)
     ap.add_argument("--no-extras", action="store_true", help="skip the step/batched extras")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=5)
+    ap.add_argument("--cpu-iters", type=int, default=12,
+                    help="iterations of the 4096^2 solve the CPU oracle runs (about 10 s)")
     ap.add_argument("--tuning", default="",
                     help="force the launch shape 'cols,tsteps,seg_rows' (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
