@@ -395,8 +395,19 @@ def _copy_ceiling(torch, f, stream):
     b.copy_(a)
     ms = timed(lambda: b.copy_(a), 5, stream, torch) / 5
     ex["copy_ceiling"] = {"gbs": round(2 * a.numel() * 4 / (ms * 1e-3) / 1e9, 1),
-                          "note": "torch copy of 1 GiB (read + write), the practical HBM ceiling"}
+                          "note": "torch copy of 1 GiB (read + write)"}
     del a, b
+    # the single update's access pattern (two planes read, one written) as a
+    # torch element-wise add over 8192^2 fp32 planes: 768 MiB, beyond the
+    # Infinity Cache
+    a = torch.rand((8192, 8192), device=f.device)
+    b = torch.rand_like(a)
+    o = torch.empty_like(a)
+    torch.add(a, b, out=o)
+    ms = timed(lambda: torch.add(a, b, out=o), 10, stream, torch) / 10
+    ex["add_ceiling_8192"] = {"gbs": round(3 * a.numel() * 4 / (ms * 1e-3) / 1e9, 1),
+                              "note": "torch add o = a + b over 8192^2 fp32 (two reads, one write)"}
+    del a, b, o
     return ex
 
 
