@@ -439,7 +439,7 @@ def _steps_t1(torch, wmc, f, lam, stream, side, want):
     if want("step_T1_8192"):
         # 8192^2 control, larger than the Infinity Cache
         g = torch.rand((1, 8192, 8192), device=f.device)
-        gbs, t1 = t1_gbs(g, 8192, 20, [(4, 4), (4, 8), (2, 4), (2, 14), (4, 12)])
+        gbs, t1 = t1_gbs(g, 8192, 20, [(4, 2), (4, 3), (4, 4), (4, 8), (2, 4), (2, 14), (4, 12)])
         ex["step_T1_8192"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                               "tuning": t1}
         del g
