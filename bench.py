@@ -190,7 +190,7 @@ def timed(fn, reps, stream, torch):
 _SPIN = {"cycles_per_ms": None}
 
 
-def timed_device(fn, reps, stream, torch):
+def timed_device(fn, reps, stream, torch, host_ms_per_call=0.5):
     """Device time of `reps` back-to-back calls of `fn`, with the host cost of
     issuing them hidden: a bounded spin kernel holds the stream while the host
     enqueues the calls, and the events bracket only the calls.  Returns
@@ -206,7 +206,7 @@ def timed_device(fn, reps, stream, torch):
     e1 = torch.cuda.Event(enable_timing=True)
     es = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    spin_ms = 5.0 + 0.5 * reps
+    spin_ms = 5.0 + host_ms_per_call * reps
     es.record(stream)
     torch.cuda._sleep(int(spin_ms * _SPIN["cycles_per_ms"]))
     e0.record(stream)
@@ -480,10 +480,15 @@ def _train(torch, wmc, wmc_synth, f, stream):
     for name, c in (("c4_train_step", None), ("c4_train_step_ckpt_sqrtK", 5)):
         train_step, x = train_step_fn(torch, wmc, wmc_synth, f.device, c)
         train_step()
-        ms_t = timed(train_step, 5, stream, torch) / 5
+        ms_t = timed(train_step, 20, stream, torch) / 20
+        # the same steps with the host's enqueueing hidden behind a spin
+        # kernel: the device time of a step
+        ms_d, hid = timed_device(train_step, 20, stream, torch, host_ms_per_call=3.0)
+        ms_d /= 20
         cc = c or wmc.wmc.default_ckpt_every(20, x.numel() * 4)
-        ms_f = timed(lambda: wmc.solve(x, lam16, 20, ckpt_every=cc), 5, stream, torch) / 5
+        ms_f = timed(lambda: wmc.solve(x, lam16, 20, ckpt_every=cc), 20, stream, torch) / 20
         ex[name] = {"ckpt_every": cc, "ms_forward_backward": round(ms_t, 3),
+                    "ms_forward_backward_device": round(ms_d, 3), "host_hidden": hid,
                     "ms_forward_ckpt": round(ms_f, 3),
                     "forward_gpx_iter_s": round(pxs / (ms_f * 1e-3) / 1e9, 1),
                     "backward_gpx_step_s": round(pxs / ((ms_t - ms_f) * 1e-3) / 1e9, 1),
