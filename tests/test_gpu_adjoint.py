@@ -219,3 +219,30 @@ def test_one_step_adjoint_shapes_and_lane_widths(wmc, monkeypatch, shape, cols):
         assert rel(g_u0[p].cpu().numpy(), res["gu0"]) <= 1e-5
         assert rel(g_f[p].cpu().numpy(), res["gf"]) <= 1e-5
         assert abs(float(g_lam[p]) - res["glam"]) <= 1e-4 * max(abs(res["glam"]), 1e-6)
+
+
+@pytest.mark.parametrize("cols", ["1", "2", "4"])
+def test_one_step_adjoint_on_tie_heavy_data(wmc, monkeypatch, cols):
+    """Dyadic images of a few grey levels, where many of the eight responses
+    tie exactly: the adjoint must take the forward's first-minimum choice at
+    every tie (a different tied candidate has a different derivative).  One
+    step, against the oracle with the forward's selection replayed."""
+    monkeypatch.setenv("WMC_ADJ_COLS", cols)
+    rng = np.random.default_rng(77)
+    H, W = 37, 131
+    u0 = rng.integers(0, 5, size=(2, H, W)) / 4.0
+    u0[:, :, 60:] = np.round(np.linspace(0.0, 1.0, W - 60) * 8) / 8.0  # dyadic ramp
+    fv = rng.integers(0, 3, size=(2, H, W)) / 2.0
+    g = rng.standard_normal((2, H, W))
+    U0, F = to_gpu(u0), to_gpu(fv)
+    lam = torch.tensor([1.0, 3.0], device="cuda:0")
+    _, ck = wmc.solve(F, lam, 1, u0=U0, ckpt_every=1)
+    g_f, g_u0, g_lam = wmc.backward(to_gpu(g), F, lam, 1, ck, 1, u0=U0)
+    _, m = wmc.step(U0, F, lam, return_argmin=True)
+    m = m.cpu().numpy().astype(np.int8)
+    for p in range(2):
+        res = oracle.solve_adjoint(g[p], fv[p].astype(np.float32), float(lam[p]), 1,
+                                   u0=u0[p].astype(np.float32), m_forced_all=m[p][None])
+        assert rel(g_u0[p].cpu().numpy(), res["gu0"]) <= 1e-5
+        assert rel(g_f[p].cpu().numpy(), res["gf"]) <= 1e-5
+        assert abs(float(g_lam[p]) - res["glam"]) <= 1e-4 * max(abs(res["glam"]), 1e-6)
