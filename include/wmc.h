@@ -207,6 +207,7 @@ size_t wmc_backward_workspace(wmc_shape s, int iters, int ckpt_every);
  *   g_lam (NULL allowed) n floats, dL/dlam_p.
  * Deterministic: the lambda sums use a fixed reduction order, no atomics.
  * ws: at least wmc_backward_workspace(s, iters, ckpt_every) bytes.
+ * Requires s.ld < 2^31 (WMC_EINVAL otherwise).
  * ------------------------------------------------------------------------- */
 int wmc_backward(const float* f, const float* u0, const float* lam, int iters, float dt,
                  const float* ckpt, int ckpt_every, const float* g_out, float* g_f, float* g_u0,

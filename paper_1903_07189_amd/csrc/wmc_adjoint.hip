@@ -132,7 +132,7 @@ struct AdjItem {
     const float* g;
     float* g_prev;
     float* g_f;
-    int64_t ld;
+    int ld;  // row stride in elements (< 2^31: row offsets are 32 x 32 -> 64-bit products)
     int H, W;
     int x0, ox0, ox1;  // first loaded column, owned columns [ox0, ox1)
     int y0, y1;        // owned rows
@@ -190,15 +190,15 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
     auto load = [&](float (&u)[C], float (&g)[C], float (&fv)[C], float (&gf)[C], int row,
                     bool any_row) {
         const int rr = row < 0 ? 0 : (row < H ? row : H - 1);
-        const float* up = it.u + (int64_t)rr * it.ld;
-        const float* gp = it.g + (int64_t)rr * it.ld;
-        const float* fp = DATA ? it.f + (int64_t)rr * it.ld : nullptr;
+        const float* up = it.u + (int64_t)rr * (int64_t)it.ld;
+        const float* gp = it.g + (int64_t)rr * (int64_t)it.ld;
+        const float* fp = DATA ? it.f + (int64_t)rr * (int64_t)it.ld : nullptr;
         // dL/df is read-modify-written on owned rows and columns only; with
         // any_row (steady steps) the row is loaded whether owned or not, at
         // clamped columns, and the values of rows and columns that are not
         // owned are never used
         if (DATA && it.g_f && (any_row || (row >= it.y0 && row < it.y1))) {
-            const float* qp = it.g_f + (int64_t)rr * it.ld;
+            const float* qp = it.g_f + (int64_t)rr * (int64_t)it.ld;
 #pragma unroll
             for (int e = 0; e < C; ++e)
                 gf[e] = any_row ? ld_at<float>(qp, (uint32_t)xc[e])
@@ -233,7 +233,7 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
     };
 
     auto store = [&](int r, const float (&acc)[C], const float (&gv)[C]) {
-        float* dp = it.g_prev + (int64_t)r * it.ld;
+        float* dp = it.g_prev + (int64_t)r * (int64_t)it.ld;
         float v[C];
 #pragma unroll
         for (int e = 0; e < C; ++e) v[e] = __builtin_fmaf(it.coef, acc[e], it.keep * gv[e]);
@@ -282,7 +282,7 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
             float G[C], W1[C], W2[C], W5[C], W6[C];
             if (ST || (rho >= 0 && rho < H)) {
                 const bool owned_row = ST || (rho >= it.y0 && rho < it.y1);
-                float* gfp = (DATA && it.g_f && owned_row) ? it.g_f + (int64_t)rho * it.ld : nullptr;
+                float* gfp = (DATA && it.g_f && owned_row) ? it.g_f + (int64_t)rho * (int64_t)it.ld : nullptr;
 #pragma unroll
                 for (int e = 0; e < C; ++e) {
                     const Odd o = parts(uw[PT].a[e], uw[PT].s[e], uw[PT].q[e], uw[PM].s[e],
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_stream(AdjArgs A) {
     it.g = A.g + off;
     it.g_prev = A.g_prev + off;
     it.g_f = (DATA && A.g_f) ? A.g_f + off : nullptr;
-    it.ld = A.ld;
+    it.ld = (int)A.ld;
     it.H = H;
     it.W = W;
     const int hb = halo_cols(C, 2), step = 64 * C - 2 * hb;

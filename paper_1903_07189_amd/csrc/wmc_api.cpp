@@ -1369,6 +1369,7 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     if (iters > 0 && !ckpt) return fail(WMC_EINVAL, "wmc_backward: checkpoints are required");
     if (!g_out) return fail(WMC_EINVAL, "wmc_backward: null g_out");
     if (!std::isfinite(dt)) return fail(WMC_EINVAL, "wmc_backward: dt must be finite");
+    if (s.ld > INT32_MAX) return fail(WMC_EINVAL, "wmc_backward: ld must be < 2^31");
     const size_t need = wmc_backward_workspace(s, iters, ckpt_every);
     if (!ws || ws_bytes < need) return fail(WMC_ENOMEM, "wmc_backward: workspace too small");
     const int64_t ext = extent_elems(s);

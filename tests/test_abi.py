@@ -145,6 +145,11 @@ def test_backward_validation(wmc):
     assert L.wmc_backward(P(4096), None, P(64), 5, 0.0, P(1 << 23), 2, P(1 << 20), P(1 << 21),
                           P(1 << 21), None, P(1 << 24), need, S, None) == wmc.WMC_EINVAL
     assert "overlap" in L.wmc_last_error().decode()
+    # the adjoint kernel takes the row stride as a 32-bit count
+    S2 = wmc.Shape(1, 8, 8, 1 << 31, 1 << 34)
+    assert L.wmc_backward(P(1 << 40), None, P(64), 5, 0.0, P(1 << 41), 2, P(1 << 42),
+                          P(1 << 43), None, None, P(1 << 44), 1 << 30, S2, None) == wmc.WMC_EINVAL
+    assert "ld" in L.wmc_last_error().decode()
 
 
 def test_valid_call_without_device_reports_hip_error(wmc):
