@@ -35,10 +35,11 @@
 // rows -1, H and columns -1, W are exactly the ring values to fold.
 //
 // dL/dlam: each work item writes one partial sum per step into its slot of
-// a buffer; k_lam_reduce adds, per plane and in a fixed order, the steps of a
-// checkpoint segment from the last to the first -- the same sequence of
-// additions whatever the segment length -- so gradients are bitwise
-// reproducible and independent of the checkpoint period.
+// a buffer; k_lam_slot_sums and k_lam_accumulate add, per plane and in a
+// fixed order, the steps of a checkpoint segment from the last to the first
+// -- the same sequence of additions whatever the segment length -- so
+// gradients are bitwise reproducible and independent of the checkpoint
+// period.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -460,44 +461,37 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_stream(AdjArgs A) {
     if (DATA && A.part && (threadIdx.x & 63) == 0) A.part[(int64_t)A.slot * total + item] = c;
 }
 
-// g_lam[p] += the step partial sums of plane p, steps from the last slot to
-// the first, each a fixed-order sum over the plane's work items (per thread
-// in item order, then a fixed tree over the 256 threads).  Up to eight steps
-// are summed side by side, so their loads are in flight together and their
-// trees share barriers; the additions and their order are those of one step
-// at a time.
-__global__ __launch_bounds__(256) void k_lam_reduce(const float* __restrict__ part, int steps,
-                                                    int64_t total, int64_t per_plane,
-                                                    float* __restrict__ g_lam) {
-    constexpr int kSide = 8;
-    const int p = blockIdx.x;
-    __shared__ float red[kSide][256];
-    for (int t_hi = steps - 1; t_hi >= 0; t_hi -= kSide) {
-        const int nb = t_hi + 1 < kSide ? t_hi + 1 : kSide;  // steps t_hi, t_hi-1, ...
-#pragma unroll
-        for (int b = 0; b < kSide; ++b) {
-            float s = 0.0f;
-            if (b < nb) {
-                const float* q = part + (int64_t)(t_hi - b) * total + (int64_t)p * per_plane;
-                for (int64_t i = threadIdx.x; i < per_plane; i += 256) s += q[i];
-            }
-            red[b][threadIdx.x] = s;
-        }
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-#pragma unroll
-                for (int b = 0; b < kSide; ++b) red[b][threadIdx.x] += red[b][threadIdx.x + w];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            float acc = g_lam[p];
-            for (int b = 0; b < nb; ++b) acc += red[b][0];
-            g_lam[p] = acc;
-        }
+// The lambda gradient in two launches.  k_lam_slot_sums: one block per
+// (step slot j, plane p) forms the slot's fixed-order sum over the plane's
+// work items (per thread in item order, then a fixed tree over the 256
+// threads) into sums[p * steps + j].  k_lam_accumulate: per plane,
+// g_lam[p] += the slot sums from the last slot to the first, one addition
+// at a time.  Every slot is reduced at once, so the launch fills the device
+// instead of running one block per plane.
+__global__ __launch_bounds__(256) void k_lam_slot_sums(const float* __restrict__ part, int64_t total,
+                                                       int64_t per_plane, int steps,
+                                                       float* __restrict__ sums) {
+    const int j = blockIdx.x, p = blockIdx.y;
+    __shared__ float red[256];
+    const float* q = part + (int64_t)j * total + (int64_t)p * per_plane;
+    float s = 0.0f;
+    for (int64_t i = threadIdx.x; i < per_plane; i += 256) s += q[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
+    if (threadIdx.x == 0) sums[(int64_t)p * steps + j] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_lam_accumulate(const float* __restrict__ sums, int steps,
+                                                        int64_t n, float* __restrict__ g_lam) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    float acc = g_lam[p];
+    for (int j = steps - 1; j >= 0; --j) acc += sums[p * steps + j];
+    g_lam[p] = acc;
 }
 
 int adj_strip_count(int W, int C) {
@@ -535,9 +529,14 @@ hipError_t launch_adjoint_step(const AdjArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_lambda_reduce(const float* part, int steps, int64_t total, int64_t per_plane,
-                                int64_t n, float* g_lam, hipStream_t st) {
-    hipLaunchKernelGGL(k_lam_reduce, dim3((unsigned)n), dim3(256), 0, st, part, steps, total,
-                       per_plane, g_lam);
+                                int64_t n, float* g_lam, float* sums, hipStream_t st) {
+    if (steps < 1 || n < 1 || n > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_lam_slot_sums, dim3((unsigned)steps, (unsigned)n), dim3(256), 0, st, part,
+                       total, per_plane, steps, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lam_accumulate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sums,
+                       steps, n, g_lam);
     return hipGetLastError();
 }
 

@@ -1343,6 +1343,14 @@ int wmc_autotune(const wmc_image* imgs, int n_imgs, int iters, wmc_tuning* out, 
 // either way.
 int lam_slots(int iters, int c) { return std::max(c, std::min(64, std::max(iters, 1))); }
 
+// Largest adjoint work-item count over the lane widths (the lambda partial
+// buffer is sized for it).
+int64_t adj_items_max(const wmc_shape& s) {
+    int64_t items = 0;
+    for (int C : {1, 2, 4}) items = std::max(items, adj_items(s.n, s.h, s.w, C));
+    return items;
+}
+
 size_t wmc_backward_workspace(wmc_shape s, int iters, int ckpt_every) {
     if (check_shape(s) || iters < 0 || ckpt_every < 1) return 0;
     const size_t set = (size_t)set_stride_elems(s) * sizeof(float);
@@ -1351,10 +1359,10 @@ size_t wmc_backward_workspace(wmc_shape s, int iters, int ckpt_every) {
     const size_t grads = 2 * set;
     // dL/dlam partial sums: one per work item and step of a segment, sized for
     // the column width with the most work items
-    int64_t items = 0;
-    for (int C : {1, 2, 4}) items = std::max(items, adj_items(s.n, s.h, s.w, C));
+    const int64_t items = adj_items_max(s);
     const size_t part = (size_t)lam_slots(iters, c) * (size_t)items * sizeof(float);
-    return states + grads + (part + 255) / 256 * 256;
+    const size_t sums = (size_t)s.n * lam_slots(iters, c) * sizeof(float);  // per-slot lambda sums
+    return states + grads + (part + 255) / 256 * 256 + sums;
 }
 
 int wmc_backward(const float* f, const float* u0, const float* lam, int iters, float dt,
@@ -1393,6 +1401,8 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     float* gB = reinterpret_cast<float*>(w);
     w += set * sizeof(float);
     float* part = reinterpret_cast<float*>(w);
+    float* lam_sums = reinterpret_cast<float*>(
+        w + ((size_t)lam_slots(iters, c) * (size_t)adj_items_max(s) * sizeof(float) + 255) / 256 * 256);
     const bool data = f != nullptr;
     // recompute launches: plain single sweeps, paired columns when aligned
     const int C1 = std::min(2, vec_cols({ckpt, states, f, u0}, s.ld, s.n > 1 ? s.ps : 0));
@@ -1474,7 +1484,7 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
             gcur = dst;
             --left;
             if (a.part && ++used == G) {
-                e = launch_lambda_reduce(part, G, items, items / s.n, s.n, g_lam, st);
+                e = launch_lambda_reduce(part, G, items, items / s.n, s.n, g_lam, lam_sums, st);
                 if (e != hipSuccess) return hip_fail(e, "lambda reduction");
                 used = 0;
             }
@@ -1482,7 +1492,7 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     }
     if (a.part && used > 0) {
         e = launch_lambda_reduce(part + (int64_t)(G - used) * items, used, items, items / s.n, s.n,
-                                 g_lam, st);
+                                 g_lam, lam_sums, st);
         if (e != hipSuccess) return hip_fail(e, "lambda reduction");
     }
     if (g_u0 && iters == 0) {

@@ -134,8 +134,11 @@ int adj_strip_count(int W, int C);
 int adj_rows(int64_t n, int64_t h, int64_t w, int C);
 int64_t adj_items(int64_t n, int64_t h, int64_t w, int C);
 hipError_t launch_adjoint_step(const AdjArgs& a, hipStream_t st);
+// Adds the lambda partial sums of `steps` step slots (slot j at part +
+// j * total, plane p's items at p * per_plane) into g_lam, the last slot
+// first; `sums` holds n * steps floats of scratch.
 hipError_t launch_lambda_reduce(const float* part, int steps, int64_t total, int64_t per_plane,
-                                int64_t n, float* g_lam, hipStream_t st);
+                                int64_t n, float* g_lam, float* sums, hipStream_t st);
 
 // Learnable half-window layer (wmc_layer.hip).
 int64_t layer_part_floats(int64_t n, int64_t h, int64_t w, int K);
