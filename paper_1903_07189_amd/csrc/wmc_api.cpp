@@ -662,34 +662,58 @@ int tune_search(Run&& run, Rows&& rows, hipStream_t st, Tuned* best_out) {
     hipEvent_t e0, e1;
     WMC_HIP(hipEventCreate(&e0), "hipEventCreate");
     WMC_HIP(hipEventCreate(&e1), "hipEventCreate");
-    double best = 1e30;
+    struct Cand {
+        double per_sweep;
+        Tuned t;
+    };
+    std::vector<Cand> cands;
     Tuned best_t{2, 4, 64};
     int rc = WMC_OK;
+    // best of three timings of `launches` back-to-back launches, per sweep
+    auto time_of = [&](const Tuned& t, int launches, double* per_sweep) -> int {
+        int r = run(t.C, t.T, t.R, st);  // warm-up
+        if (r) return r;
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            WMC_HIP(hipEventRecord(e0, st), "hipEventRecord");
+            for (int l = 0; l < launches; ++l) {
+                r = run(t.C, t.T, t.R, st);
+                if (r) return r;
+            }
+            WMC_HIP(hipEventRecord(e1, st), "hipEventRecord");
+            WMC_HIP(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.0f;
+            WMC_HIP(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            ms_best = std::min(ms_best, ms);
+        }
+        *per_sweep = ms_best / ((double)t.T * launches);
+        return WMC_OK;
+    };
+    // every candidate on single launches, then the four fastest again on
+    // runs of eight launches, which the single-launch figures rank
+    // unreliably when candidates are within a few per cent
     for (int C : {1, 2, 4})
         for (int T : {1, 2, 3, 4, 6, 8})
             for (int R : rows(C, T)) {
-                // warm up once, then take the best of three
-                rc = run(C, T, R, st);
+                double ps = 0.0;
+                rc = time_of(Tuned{C, T, R}, 1, &ps);
                 if (rc) goto done;
-                {
-                    float ms_best = 1e30f;
-                    for (int rep = 0; rep < 3; ++rep) {
-                        WMC_HIP(hipEventRecord(e0, st), "hipEventRecord");
-                        rc = run(C, T, R, st);
-                        if (rc) goto done;
-                        WMC_HIP(hipEventRecord(e1, st), "hipEventRecord");
-                        WMC_HIP(hipEventSynchronize(e1), "hipEventSynchronize");
-                        float ms = 0.0f;
-                        WMC_HIP(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-                        ms_best = std::min(ms_best, ms);
-                    }
-                    const double per_sweep = ms_best / T;
-                    if (per_sweep < best) {
-                        best = per_sweep;
-                        best_t = {C, T, R};
-                    }
-                }
+                cands.push_back({ps, Tuned{C, T, R}});
             }
+    std::sort(cands.begin(), cands.end(),
+              [](const Cand& x, const Cand& y) { return x.per_sweep < y.per_sweep; });
+    {
+        double best = 1e30;
+        for (size_t i = 0; i < cands.size() && i < 4; ++i) {
+            double ps = 0.0;
+            rc = time_of(cands[i].t, 8, &ps);
+            if (rc) goto done;
+            if (ps < best) {
+                best = ps;
+                best_t = cands[i].t;
+            }
+        }
+    }
 done:
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
