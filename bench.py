@@ -341,7 +341,7 @@ def main():
 
 EXTRA_NAMES = ("copy_ceiling", "step_T1_4096", "step_T1_8192", "compute_4096", "fd_4096", "l1_4096",
                "step_T1_4096_cold", "c4_train_step", "volume_256cubed", "layer_k8_16x512",
-               "batched_c3")
+               "batched_c3", "c1_256")
 
 
 def extras(torch, wmc, wmc_synth, f, lam, stream, side, only=None):
@@ -382,6 +382,18 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side, only=None):
         ex.update(_volume(torch, wmc, f, stream))
     if want("layer_k8_16x512"):
         ex.update(_layer(torch, wmc, wmc_synth, f, stream))
+    if want("c1_256"):
+        # the 256 x 256 parity workload (seed 0, sigma 0.05, lam 1, 50
+        # iterations): one graph-replayed solve, autotuned
+        c1, _ = wmc_synth.c1()
+        g1 = torch.from_numpy(c1).to(f.device)
+        p1 = wmc.SolvePlan(g1, lam, 50, tuning=wmc.solve_tuning(g1, lam))
+        p1()
+        ms = timed(p1, 50, stream, torch) / 50
+        ex["c1_256"] = {"ms_per_solve": round(ms, 4),
+                        "gpx_iter_s": round(256 * 256 * 50 / (ms * 1e-3) / 1e9, 2),
+                        "note": "256x256 fp32, 50 iterations, one graph replay per solve"}
+        del g1
     if want("batched_c3"):
         ex.update(_batched(torch, wmc, wmc_synth, f, stream))
     return ex
