@@ -215,6 +215,15 @@ std::vector<int> candidate_rows(int64_t planes, int64_t h, int64_t w, int C, int
     }
     add(16);
     add(32);
+    // a problem too small to fill one round of resident waves even at a
+    // few rows per item: its launches last about one item's serial latency,
+    // so short items win despite their recomputed ramp rows (256 x 256,
+    // 50 iterations: 0.27 ms at 16 rows per item, 0.11 ms at 2)
+    if (rows_for_rounds(planes, h, w, C, T, slots, 1) < 16) {
+        add(std::min<int>((int)h, 2));
+        add(std::min<int>((int)h, 4));
+        add(std::min<int>((int)h, 8));
+    }
     return out;
 }
 
