@@ -1053,7 +1053,11 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
         rc = resolve_tuning(tune, Tuned{2, 4, 64}, &t, &graph);
     } else {
         Tuned auto_t{};
-        rc = tune_single(dev, s, src0, f, lam, dt, iters >= 2 ? static_cast<float*>(ws) : u_out, st,
+        // with a workspace the candidates read U from u_out (contents
+        // irrelevant to the timing) rather than from f, so that, as in the
+        // solve, U and f are different planes
+        rc = tune_single(dev, s, iters >= 2 ? u_out : src0, f, lam, dt,
+                         iters >= 2 ? static_cast<float*>(ws) : u_out, st,
                          &auto_t);
         if (rc) return rc;
         rc = resolve_tuning(tune, auto_t, &t, &graph);
@@ -1159,8 +1163,15 @@ int wmc_solve_l1(const float* f, const float* u0, const float* d0, float* u_out,
         auto search = [&](Tuned* out) {
             float* scratchU = iters >= 2 ? wsU : u_out;
             float* scratchD = iters >= 2 ? wsD : d_out;
+            // time launches shaped like the solve's: U and f different
+            // planes, and a dual plane read (every launch after the first
+            // reads one).  With a workspace, u_out and d_out serve as those
+            // planes (their contents do not matter for the timing; the
+            // solve overwrites them)
+            const float* usrc = iters >= 2 ? u_out : src0;
+            const float* dsrc = iters >= 2 ? d_out : d0;
             auto run = [&](int C, int T, int R, hipStream_t ss) {
-                return enqueue_l1(s, src0, d0, f, scratchU, scratchD, lam, alpha, dt, C, T, R, ss);
+                return enqueue_l1(s, usrc, dsrc, f, scratchU, scratchD, lam, alpha, dt, C, T, R, ss);
             };
             auto rows = [&](int C, int T) {
                 return candidate_rows(s.n, s.h, s.w, C, T, dev, kModeL1);
