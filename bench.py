@@ -341,7 +341,7 @@ def main():
 
 EXTRA_NAMES = ("copy_ceiling", "step_T1_4096", "step_T1_8192", "compute_4096", "fd_4096", "l1_4096",
                "step_T1_4096_cold", "c4_train_step", "volume_256cubed", "layer_k8_16x512",
-               "batched_c3", "c1_256")
+               "batched_c3", "c1_256", "c5_train_step")
 
 
 def extras(torch, wmc, wmc_synth, f, lam, stream, side, only=None):
@@ -394,6 +394,26 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side, only=None):
                         "gpx_iter_s": round(256 * 256 * 50 / (ms * 1e-3) / 1e9, 2),
                         "note": "256x256 fp32, 50 iterations, one graph replay per solve"}
         del g1
+    if want("c5_train_step"):
+        # one optimiser step of the learned-lambda workload: 32 x 256^2
+        # (seed 3000), lambda from an 8-entry table, K = 30, default
+        # checkpoint period, MSE loss, backward to the table
+        noisy, clean, _ = wmc_synth.c5_batch(3000, batch=32)
+        x5 = torch.from_numpy(noisy[:, 0]).to(f.device)
+        y5 = torch.from_numpy(clean[:, 0]).to(f.device)
+        theta = torch.zeros(8, device=f.device, requires_grad=True)
+        k5 = torch.arange(32, device=f.device) % 8
+
+        def step5():
+            u = wmc.WMCSolve.apply(x5, torch.exp(theta)[k5], 30)
+            torch.mean((u - y5) ** 2).backward()
+        step5()
+        ms = timed(step5, 20, stream, torch) / 20
+        ms_d, hid = timed_device(step5, 20, stream, torch, host_ms_per_call=3.0)
+        ex["c5_train_step"] = {"ms": round(ms, 3), "ms_device": round(ms_d / 20, 3),
+                               "host_hidden": hid,
+                               "note": "32x256^2, K=30, forward + MSE + backward to the lambda table"}
+        del x5, y5
     if want("batched_c3"):
         ex.update(_batched(torch, wmc, wmc_synth, f, stream))
     return ex
