@@ -139,6 +139,7 @@ struct AdjItem {
     int y0, y1;        // owned rows
     float delta, lam, keep, coef;
     bool dlam_default;  // delta = 1/(1+lam): dU'/dlam has the delta'(lam) term
+    bool gf_first;      // g_f is not read (taken as zero) but written
 };
 
 template <int P>
@@ -198,7 +199,7 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
         // any_row (steady steps) the row is loaded whether owned or not, at
         // clamped columns, and the values of rows and columns that are not
         // owned are never used
-        if (DATA && it.g_f && (any_row || (row >= it.y0 && row < it.y1))) {
+        if (DATA && it.g_f && !it.gf_first && (any_row || (row >= it.y0 && row < it.y1))) {
             const float* qp = it.g_f + (int64_t)rr * (int64_t)it.ld;
 #pragma unroll
             for (int e = 0; e < C; ++e)
@@ -307,7 +308,8 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
                             const float c1 = __builtin_fmaf(gv, dudl, contrib);
                             contrib = own[e] ? c1 : contrib;
                             if (gfp && own[e])
-                                st_at<float>(gfp, (uint32_t)(xb + e), __builtin_fmaf(it.delta, gv, gfr[PM][e]));
+                                st_at<float>(gfp, (uint32_t)(xb + e),
+                                             __builtin_fmaf(it.delta, gv, it.gf_first ? 0.0f : gfr[PM][e]));
                         }
                     }
                 }
@@ -453,6 +455,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_stream(AdjArgs A) {
     it.keep = DATA ? 1.0f - cf.delta : 1.0f;
     it.coef = DATA ? cf.delta * cf.lam12 : cf.delta12;
     it.dlam_default = !(A.dt > 0.0f);
+    it.gf_first = A.gf_first != 0;
     const bool edge = it.x0 < 0 || it.x0 + 64 * C > W;
     float c;
     if (edge) c = run_adj<C, DATA, true, false>(it);

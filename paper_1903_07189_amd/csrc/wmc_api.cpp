@@ -1487,10 +1487,13 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
         e = launch_fill_f32(g_lam, s.n, 0.0f, st);
         if (e != hipSuccess) return hip_fail(e, "fill");
     }
-    if (data && g_f) {
+    // dL/df: the first adjoint step writes it without reading it (every
+    // pixel is owned by one work item); with no step it starts at zero
+    if (data && g_f && iters == 0) {
         e = launch_fill_f32(g_f, (s.n - 1) * s.ps + (s.h - 1) * s.ld + s.w, 0.0f, st);
         if (e != hipSuccess) return hip_fail(e, "fill");
     }
+    a.gf_first = 1;
     // the first adjoint step reads g_out itself; the steps then alternate
     // between gA and gB, and the last one writes g_u0 when it is wanted
     const float* gcur = g_out;
@@ -1524,6 +1527,7 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
             a.slot = G - 1 - used;
             e = launch_adjoint_step(a, st);
             if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+            a.gf_first = 0;
             if (dst == gbuf[gnext]) gnext ^= 1;
             gcur = dst;
             --left;
