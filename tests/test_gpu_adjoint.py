@@ -246,3 +246,19 @@ def test_one_step_adjoint_on_tie_heavy_data(wmc, monkeypatch, cols):
         assert rel(g_u0[p].cpu().numpy(), res["gu0"]) <= 1e-5
         assert rel(g_f[p].cpu().numpy(), res["gf"]) <= 1e-5
         assert abs(float(g_lam[p]) - res["glam"]) <= 1e-4 * max(abs(res["glam"]), 1e-6)
+
+
+def test_rows_per_item_override(wmc, monkeypatch):
+    """WMC_ADJ_ROWS (more rows per adjoint work item than the default) gives
+    the same gradients: dL/df bitwise (per-pixel arithmetic is unchanged),
+    dL/dlam to rounding (its partial sums group the pixels differently)."""
+    rng = np.random.default_rng(5)
+    f = to_gpu(rng.uniform(0, 1, size=(2, 90, 70)))
+    lam = torch.tensor([1.0, 2.0], device="cuda:0")
+    uK, ck = wmc.solve(f, lam, 6, ckpt_every=2)
+    g = to_gpu(rng.standard_normal((2, 90, 70)))
+    ref = wmc.backward(g, f, lam, 6, ck, 2)
+    monkeypatch.setenv("WMC_ADJ_ROWS", "40")
+    got = wmc.backward(g, f, lam, 6, ck, 2)
+    assert torch.equal(got[0], ref[0])
+    assert torch.allclose(got[2], ref[2], rtol=1e-5, atol=0.0)
