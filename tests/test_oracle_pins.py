@@ -543,6 +543,124 @@ def test_adjoint_fixed_delta_lambda_gradient():
     assert fd == pytest.approx(res["glam"], rel=1e-5, abs=1e-9)
 
 
+# Away from lam = 1 the data-term factors differ: delta = 1/(1+lam) != 1 - delta and
+# delta^2 != delta(1 - delta), so a swapped keep factor, a (1 - delta) in place of
+# delta in dL/df or a wrong derivative of the default step fails here.  Starting
+# from u0 != f separates dL/df (the data term, Sec. 5.2 update) from dL/dU^0.
+
+def _path_maps(f, u0, lam, delta, K):
+    """Selection maps along a K-step solve from u0 (f None: flow)."""
+    maps, u = [], u0.copy()
+    for _ in range(K):
+        u, m = oracle.step(u, f, lam, delta, return_argmin=True)
+        maps.append(m)
+    return maps
+
+
+def _fd_pins(f, u0, target, lam, delta, K, delta_follows_lam, rng, n_pix=14):
+    """Central differences (h = 1e-6, FP64) of L = 1/2 ||U^K - target||^2 with
+    respect to single entries of f and of u0 separately, and to lam, against
+    the oracle adjoint.  Perturbations that change a selection anywhere along
+    the path are skipped (the map is piecewise affine)."""
+    H, W = u0.shape
+    h = 1e-6
+
+    def dlt(ll):
+        return 1.0 / (1.0 + ll) if delta_follows_lam else delta
+
+    def run(ff, uu, ll):
+        return oracle.solve(ff, lam=ll, iters=K, delta=dlt(ll), u0=uu)
+
+    UK = run(f, u0, lam)
+    res = oracle.solve_adjoint(UK - target, f, lam, K, delta=dlt(lam), u0=u0,
+                               delta_from_lam=delta_follows_lam)
+    base = _path_maps(f, u0, lam, dlt(lam), K)
+    checked = {"f": 0, "u0": 0}
+    for which in ("f", "u0"):
+        if which == "f" and f is None:
+            continue
+        for _ in range(n_pix):
+            y, x = int(rng.integers(H)), int(rng.integers(W))
+            runs = []
+            for sgn in (1.0, -1.0):
+                ff = None if f is None else f.copy()
+                uu = u0.copy()
+                (ff if which == "f" else uu)[y, x] += sgn * h
+                runs.append((ff, uu))
+            if any(not all(np.array_equal(a, b) for a, b in
+                           zip(_path_maps(ff, uu, lam, dlt(lam), K), base)) for ff, uu in runs):
+                continue
+            fd = (_loss(run(*runs[0], lam), target) - _loss(run(*runs[1], lam), target)) / (2 * h)
+            want = res["gf"][y, x] if which == "f" else res["gu0"][y, x]
+            assert fd == pytest.approx(want, rel=1e-5, abs=1e-9), (which, y, x)
+            checked[which] += 1
+    if f is not None:
+        assert checked["f"] >= n_pix // 2
+        fdl = (_loss(run(f, u0, lam + h), target) - _loss(run(f, u0, lam - h), target)) / (2 * h)
+        assert fdl == pytest.approx(res["glam"], rel=1e-5, abs=1e-9)
+    assert checked["u0"] >= n_pix // 2
+    return res
+
+
+@pytest.mark.parametrize("lam", [0.3, 2.5])
+def test_adjoint_fd_default_step_away_from_lambda_one(lam):
+    rng = np.random.default_rng(int(lam * 10) + 30)
+    H, W, K = 8, 9, 5
+    f = rng.uniform(0, 1, size=(H, W))
+    u0 = rng.uniform(0, 1, size=(H, W))
+    target = rng.uniform(0, 1, size=(H, W))
+    res = _fd_pins(f, u0, target, lam, None, K, True, rng)
+    # the two parts really differ: dL/df is not dL/dU^0 (u0 != f)
+    assert np.abs(res["gf"] - res["gu0"]).max() > 1e-3
+
+
+def test_adjoint_fd_default_step_u0_is_f_lambda_2_5():
+    """Starting from U^0 = f, dL/df is the data-term part plus dL/dU^0."""
+    rng = np.random.default_rng(33)
+    H, W, K, lam = 7, 10, 6, 2.5
+    f = rng.uniform(0, 1, size=(H, W))
+    target = rng.uniform(0, 1, size=(H, W))
+    UK = oracle.solve(f, lam=lam, iters=K)
+    res = oracle.solve_adjoint(UK - target, f, lam, K)
+    total = res["gf"] + res["gu0"]
+    base = _path_maps(f, f, lam, 1 / (1 + lam), K)
+    h, checked = 1e-6, 0
+    for _ in range(16):
+        y, x = int(rng.integers(H)), int(rng.integers(W))
+        fp, fm = f.copy(), f.copy()
+        fp[y, x] += h
+        fm[y, x] -= h
+        if not all(all(np.array_equal(a, b) for a, b in zip(_path_maps(ff, ff, lam, 1 / (1 + lam), K),
+                                                            base)) for ff in (fp, fm)):
+            continue
+        fd = (_loss(oracle.solve(fp, lam=lam, iters=K), target)
+              - _loss(oracle.solve(fm, lam=lam, iters=K), target)) / (2 * h)
+        assert fd == pytest.approx(total[y, x], rel=1e-5, abs=1e-9)
+        checked += 1
+    assert checked >= 8
+
+
+def test_adjoint_fd_explicit_step():
+    """An explicit step delta (here 0.2 at lam = 2.5, delta (1 + lam) = 0.7):
+    the keep factor is 1 - delta, the data factor delta, and only delta H_d
+    enters dL/dlam."""
+    rng = np.random.default_rng(34)
+    H, W, K = 9, 8, 5
+    f = rng.uniform(0, 1, size=(H, W))
+    u0 = rng.uniform(0, 1, size=(H, W))
+    target = rng.uniform(0, 1, size=(H, W))
+    _fd_pins(f, u0, target, 2.5, 0.2, K, False, rng)
+
+
+def test_adjoint_fd_flow_mode():
+    """Curvature flow (no data term), delta = 0.6: dL/dU^0 by central differences."""
+    rng = np.random.default_rng(35)
+    H, W, K = 8, 8, 4
+    u0 = rng.uniform(0, 1, size=(H, W))
+    target = rng.uniform(0, 1, size=(H, W))
+    _fd_pins(None, u0, target, 1.0, 0.6, K, False, rng)
+
+
 # ---------------------------------------------------------------------------------------
 # brute force on tiny inputs: the selection is the first minimum in printed order
 # ---------------------------------------------------------------------------------------
@@ -610,6 +728,32 @@ def test_energy_closed_forms():
     ramp = np.tile(a * np.arange(W, dtype=np.float64), (H, 1))
     want = lam * (H * (W - 1) * np.sqrt(1 + a * a) + H)
     assert oracle.energy_area(ramp, None, lam) == pytest.approx(want, rel=1e-14)
+    # the same ramp along y, and a plane a x + b y: interior pixels have
+    # |grad|^2 = a^2 + b^2, the last column b^2 only, the last row a^2 only
+    ramp_y = ramp.T.copy()
+    want_y = lam * (H * (W - 1) * np.sqrt(1 + a * a) + H)
+    assert oracle.energy_area(ramp_y, None, lam) == pytest.approx(want_y, rel=1e-14)
+    b = -0.4
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    plane = a * xx + b * yy
+    want_p = lam * ((H - 1) * (W - 1) * np.sqrt(1 + a * a + b * b)
+                    + (H - 1) * np.sqrt(1 + b * b) + (W - 1) * np.sqrt(1 + a * a) + 1)
+    assert oracle.energy_area(plane, None, lam) == pytest.approx(want_p, rel=1e-14)
+
+
+def test_energy_area_matches_an_independent_evaluation():
+    """eq. (areaReg) with forward differences (zero at the last row and column)
+    plus the quadratic data term, evaluated with numpy array slicing."""
+    rng = np.random.default_rng(3)
+    u = rng.uniform(0, 1, size=(13, 17))
+    f = rng.uniform(0, 1, size=(13, 17))
+    lam = 5.0
+    ux = np.zeros_like(u)
+    uy = np.zeros_like(u)
+    ux[:, :-1] = u[:, 1:] - u[:, :-1]
+    uy[:-1, :] = u[1:, :] - u[:-1, :]
+    e = (0.5 * (u - f) ** 2 + lam * np.sqrt(1.0 + ux * ux + uy * uy)).sum()
+    assert oracle.energy_area(u, f, lam) == pytest.approx(e, rel=1e-13)
 
 
 def test_near_tie_helpers():
