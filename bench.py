@@ -157,11 +157,11 @@ def aggregate_oracle(max_procs: int = 16, iters: int = 2):
                       f"(slowest {slowest:.1f} s, wall incl. start-up {wall:.1f} s)"}
 
 
-def train_step_fn(torch, wmc, wmc_synth, dev, ckpt_every=None):
+def train_step_fn(torch, wmc, wmc_synth, dev, ckpt_every=5):
     """One optimisation step's worth of work on the 16 x 512 x 512, K = 20
-    workload: the fused forward with checkpoints (default period: every state
-    while they fit the budget, else ceil(sqrt(K))), the MSE loss against the
-    clean images, and backward through the adjoint to f and lam."""
+    workload: the fused forward with checkpoints (every ceil(sqrt(K)) = 5
+    steps unless given), the MSE loss against the clean images, and backward
+    through the adjoint to f and lam."""
     noisy, clean = wmc_synth.c4()
     x = torch.from_numpy(noisy[:, 0]).to(dev)
     y = torch.from_numpy(clean[:, 0]).to(dev)
@@ -396,8 +396,8 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side, only=None):
         del g1
     if want("c5_train_step"):
         # one optimiser step of the learned-lambda workload: 32 x 256^2
-        # (seed 3000), lambda from an 8-entry table, K = 30, default
-        # checkpoint period, MSE loss, backward to the table
+        # (seed 3000), lambda from an 8-entry table, K = 30, a checkpoint
+        # every ceil(sqrt(K)) = 6 steps, MSE loss, backward to the table
         noisy, clean, _ = wmc_synth.c5_batch(3000, batch=32)
         x5 = torch.from_numpy(noisy[:, 0]).to(f.device)
         y5 = torch.from_numpy(clean[:, 0]).to(f.device)
@@ -405,13 +405,14 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side, only=None):
         k5 = torch.arange(32, device=f.device) % 8
 
         def step5():
-            u = wmc.WMCSolve.apply(x5, torch.exp(theta)[k5], 30)
+            u = wmc.WMCSolve.apply(x5, torch.exp(theta)[k5], 30, 0.0, 6)
             torch.mean((u - y5) ** 2).backward()
         step5()
         ms = timed(step5, 20, stream, torch) / 20
         ms_d, hid = timed_device(step5, 20, stream, torch, host_ms_per_call=3.0)
         ex["c5_train_step"] = {"ms": round(ms, 3), "ms_device": round(ms_d / 20, 3),
                                "host_hidden": hid,
+                               "ckpt_every": 6,
                                "note": "32x256^2, K=30, forward + MSE + backward to the lambda table"}
         del x5, y5
     if want("batched_c3"):
@@ -509,7 +510,7 @@ def _train(torch, wmc, wmc_synth, f, stream):
     # training step = fused forward with checkpoints + hand-written adjoint
     pxs = 16 * 512 * 512 * 20
     lam16 = torch.ones(16, device=f.device)
-    for name, c in (("c4_train_step", None), ("c4_train_step_ckpt_sqrtK", 5)):
+    for name, c in (("c4_train_step", 5), ("c4_train_step_every_state", 1)):
         train_step, x = train_step_fn(torch, wmc, wmc_synth, f.device, c)
         train_step()
         ms_t = timed(train_step, 20, stream, torch) / 20
@@ -524,9 +525,10 @@ def _train(torch, wmc, wmc_synth, f, stream):
                     "ms_forward_ckpt": round(ms_f, 3),
                     "forward_gpx_iter_s": round(pxs / (ms_f * 1e-3) / 1e9, 1),
                     "backward_gpx_step_s": round(pxs / ((ms_t - ms_f) * 1e-3) / 1e9, 1),
-                    "note": "c4_train_step uses the library's default checkpoint period; "
-                            "backward = segment recompute (none at period 1) + adjoint steps "
-                            "+ lam reduction"}
+                    "note": "c4_train_step checkpoints every ceil(sqrt(K)) = 5 steps; "
+                            "c4_train_step_every_state keeps every state (period 1, the "
+                            "library's default while K states fit 2 GiB); backward = segment "
+                            "recompute (none at period 1) + adjoint steps + lam reduction"}
         del x
     return ex
 

@@ -249,7 +249,8 @@ int wmc_layer_backward(const float* u, const float* w, int K, const uint8_t* sel
  * vanish where the gradient does (H^w then tends to the Laplacian).
  * wmc_fd_flow -- iters explicit curvature-flow steps U <- U + dt H^w_fd(U)
  * from u0 (ws: wmc_solve_workspace(s) bytes when iters >= 2).
- * Comparator kernels: one thread per pixel, not temporally blocked.
+ * Comparator kernels: one wave per strip of columns streaming down the rows
+ * (one sweep per launch, not temporally blocked).
  * ------------------------------------------------------------------------- */
 int wmc_fd_compute(const float* u, float* hw, float eps, wmc_shape s, void* stream);
 int wmc_fd_flow(const float* u0, float* u_out, int iters, float dt, float eps, void* ws,

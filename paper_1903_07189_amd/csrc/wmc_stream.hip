@@ -437,22 +437,29 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
     if (i < n) p[i] = v;
 }
 
-__global__ void k_add_planes(const float* __restrict__ src, float* __restrict__ dst, int64_t h,
-                             int64_t w, int64_t ld, int64_t ps) {
-    const int64_t p = blockIdx.z;
-    const int64_t y = blockIdx.y;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < w;
-         x += (int64_t)gridDim.x * blockDim.x)
-        dst[p * ps + y * ld + x] += src[p * ps + y * ld + x];
+// Plane-set copy and accumulate: the rows of all planes (p, y) form one list
+// that the grid's y dimension strides over, so any height and plane count
+// fits the launch; threads run along the row.
+__global__ void k_add_planes(const float* __restrict__ src, float* __restrict__ dst, int64_t rows,
+                             int64_t h, int64_t w, int64_t ld, int64_t ps) {
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        const int64_t p = r / h;
+        const int64_t base = p * ps + (r - p * h) * ld;
+        for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < w;
+             x += (int64_t)gridDim.x * blockDim.x)
+            dst[base + x] += src[base + x];
+    }
 }
 
-__global__ void k_copy_planes(const float* __restrict__ src, float* __restrict__ dst, int64_t h,
-                              int64_t w, int64_t ld, int64_t ps) {
-    const int64_t p = blockIdx.z;
-    const int64_t y = blockIdx.y;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < w;
-         x += (int64_t)gridDim.x * blockDim.x)
-        dst[p * ps + y * ld + x] = src[p * ps + y * ld + x];
+__global__ void k_copy_planes(const float* __restrict__ src, float* __restrict__ dst, int64_t rows,
+                              int64_t h, int64_t w, int64_t ld, int64_t ps) {
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        const int64_t p = r / h;
+        const int64_t base = p * ps + (r - p * h) * ld;
+        for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < w;
+             x += (int64_t)gridDim.x * blockDim.x)
+            dst[base + x] = src[base + x];
+    }
 }
 
 // Lane-shift self test: flags[w] = 1 iff the lane shifts of wmc_device.hpp
@@ -652,23 +659,27 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Grid of the plane-set copy / accumulate: up to 64 blocks along a row and
+// up to 65535 along the row list (the kernels stride over the rest).
+static dim3 plane_rows_grid(int64_t rows, int64_t w) {
+    const int64_t gx = (w + 255) / 256 < 64 ? (w + 255) / 256 : 64;
+    const int64_t gy = rows < 65535 ? rows : 65535;
+    return dim3((unsigned)gx, (unsigned)gy);
+}
+
 hipError_t launch_copy_planes(const float* src, float* dst, int64_t n, int64_t h, int64_t w,
                               int64_t ld, int64_t ps, hipStream_t st) {
     if (n <= 0 || h <= 0 || w <= 0) return hipSuccess;
-    const int64_t gx = (w + 255) / 256 < 64 ? (w + 255) / 256 : 64;
-    if (h > 65535 || n > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_copy_planes, dim3((unsigned)gx, (unsigned)h, (unsigned)n), dim3(256), 0,
-                       st, src, dst, h, w, ld, ps);
+    hipLaunchKernelGGL(k_copy_planes, plane_rows_grid(n * h, w), dim3(256), 0, st, src, dst, n * h,
+                       h, w, ld, ps);
     return hipGetLastError();
 }
 
 hipError_t launch_add_planes(const float* src, float* dst, int64_t n, int64_t h, int64_t w,
                              int64_t ld, int64_t ps, hipStream_t st) {
     if (n <= 0 || h <= 0 || w <= 0) return hipSuccess;
-    const int64_t gx = (w + 255) / 256 < 64 ? (w + 255) / 256 : 64;
-    if (h > 65535 || n > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_add_planes, dim3((unsigned)gx, (unsigned)h, (unsigned)n), dim3(256), 0,
-                       st, src, dst, h, w, ld, ps);
+    hipLaunchKernelGGL(k_add_planes, plane_rows_grid(n * h, w), dim3(256), 0, st, src, dst, n * h,
+                       h, w, ld, ps);
     return hipGetLastError();
 }
 

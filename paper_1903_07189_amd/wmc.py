@@ -18,7 +18,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libwmc.so")
+# WMC_LIB names another build of the same library (for instance one whose host
+# code is compiled with sanitizers); by default the in-tree libwmc.so.
+LIB_PATH = os.environ.get("WMC_LIB") or os.path.join(_HERE, "libwmc.so")
 
 WMC_OK, WMC_EINVAL, WMC_EHIP, WMC_ENOMEM, WMC_EUNSUPPORTED = 0, -1, -2, -3, -4
 WMC_OP_SOLVE, WMC_OP_SOLVE_L1, WMC_OP_BACKWARD, WMC_OP_FD_FLOW, WMC_OP_LAYER_BACKWARD = 0, 1, 2, 3, 4
@@ -153,6 +155,21 @@ def shape_of(t: torch.Tensor) -> Shape:
     return Shape(n, h, w, t.stride(1), t.stride(0) if n > 1 else h * t.stride(1))
 
 
+def require_shape(t: torch.Tensor | None, want, name: str) -> None:
+    """Raises ValueError unless t (if given) has exactly the shape `want`.
+    Every array passed with one wmc_shape must cover that shape: a tensor with
+    fewer planes or rows would be read past its end by the kernels."""
+    if t is not None and tuple(t.shape) != tuple(want):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(want)}")
+
+
+def checkpoint_sets(iters: int, ckpt_every: int) -> int:
+    """Plane sets a solve(..., ckpt_every=c) of iters steps returns (at least one)."""
+    if int(ckpt_every) < 1:
+        raise ValueError("ckpt_every must be >= 1")
+    return max(1, int(lib().wmc_num_checkpoints(int(iters), int(ckpt_every))))
+
+
 def _like(t: torch.Tensor) -> torch.Tensor:
     """Uninitialised tensor with exactly t's strides (the ABI shares one layout)."""
     return torch.empty_strided(t.shape, t.stride(), dtype=t.dtype, device=t.device)
@@ -195,7 +212,8 @@ def step(u: torch.Tensor, f: torch.Tensor | None = None, lam=1.0, dt: float = 0.
     u = _planes(u)
     if f is not None:
         f = _planes(f)
-        if f.shape != u.shape or f.stride() != u.stride():
+        require_shape(f, u.shape, "f")
+        if f.stride() != u.stride():
             f = f.contiguous() if u.is_contiguous() else f
             if f.stride() != u.stride():
                 raise ValueError("u and f must share shape and layout")
@@ -223,6 +241,7 @@ def solve(f: torch.Tensor | None, lam=1.0, iters: int = 1, dt: float = 0.0,
     ref = _planes(ref).contiguous()
     f = None if f is None else _planes(f).contiguous()
     u0 = None if u0 is None else _planes(u0).contiguous()
+    require_shape(u0, ref.shape, "u0")
     s = shape_of(ref)
     L = lib()
     out = torch.empty_like(ref)
@@ -250,6 +269,8 @@ def solve_l1(f: torch.Tensor, lam=1.0, alpha: float = 0.05, iters: int = 1, dt: 
     f = _planes(f).contiguous()
     u0 = None if u0 is None else _planes(u0).contiguous()
     d0 = None if d0 is None else _planes(d0).contiguous()
+    require_shape(u0, f.shape, "u0")
+    require_shape(d0, f.shape, "d0")
     s = shape_of(f)
     L = lib()
     out, dout = torch.empty_like(f), torch.empty_like(f)
@@ -386,6 +407,7 @@ def solve3(f: torch.Tensor | None, lam=1.0, iters: int = 1, dt: float = 0.0,
     ref = _volumes(ref)
     f = None if f is None else _volumes(f)
     u0 = None if u0 is None else _volumes(u0)
+    require_shape(u0, ref.shape, "u0")
     s = shape3_of(ref)
     L = lib()
     out = torch.empty_like(ref)
@@ -402,6 +424,7 @@ def solve_tuning(f: torch.Tensor | None, lam=1.0, dt: float = 0.0, u0: torch.Ten
     ref = _planes(ref).contiguous()
     f = None if f is None else _planes(f).contiguous()
     u0 = None if u0 is None else _planes(u0).contiguous()
+    require_shape(u0, ref.shape, "u0")
     s = shape_of(ref)
     L = lib()
     ws = torch.empty(max(1, L.wmc_solve_workspace(s) // 4), dtype=torch.float32, device=ref.device)
@@ -439,10 +462,19 @@ def backward(g_out: torch.Tensor, f: torch.Tensor | None, lam, iters: int, ckpt:
     """Reverse-mode derivative of L(U^iters) through solve(); returns
     (g_f, g_u0, g_lam).  g_f includes the path through U^0 = f when u0 is None."""
     ref = f if f is not None else u0
+    if ref is None:
+        raise ValueError("need f or u0")
     ref = _planes(ref).contiguous()
     f = None if f is None else _planes(f).contiguous()
     u0 = None if u0 is None else _planes(u0).contiguous()
     g_out = _planes(g_out).contiguous()
+    require_shape(u0, ref.shape, "u0")
+    require_shape(g_out, ref.shape, "g_out")
+    if ckpt is None:
+        raise ValueError("backward needs the checkpoints of the forward solve")
+    if ckpt.dtype != torch.float32 or not ckpt.is_cuda or not ckpt.is_contiguous():
+        raise ValueError("ckpt must be a contiguous float32 CUDA tensor")
+    require_shape(ckpt, (checkpoint_sets(iters, ckpt_every),) + tuple(ref.shape), "ckpt")
     s = shape_of(ref)
     L = lib()
     n = ref.shape[0]
@@ -474,7 +506,12 @@ def solve_batched(fs, lam, iters: int, dt: float = 0.0, u0s=None, tuning=None):
     fs = [None if f is None else _planes(f).contiguous() for f in fs]
     u0s = [None] * len(fs) if u0s is None else [None if u is None else _planes(u).contiguous()
                                                  for u in u0s]
+    if len(u0s) != len(fs):
+        raise ValueError("u0s must hold one entry per image")
     refs = [f if f is not None else u for f, u in zip(fs, u0s)]
+    for i, (f, u) in enumerate(zip(fs, u0s)):
+        if f is not None:
+            require_shape(u, f.shape, f"u0s[{i}]")
     dev = refs[0].device
     outs = [torch.empty_like(r) for r in refs]
     lt = _lam_tensor(lam, len(fs), dev) if fs[0] is not None else None

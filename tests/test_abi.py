@@ -164,6 +164,26 @@ def test_valid_call_without_device_reports_hip_error(wmc):
     assert L.wmc_last_error()
 
 
+def test_tall_images_pass_validation(wmc):
+    """Images taller than 65535 rows are valid for the solve and the backward
+    (their plane copies stride over rows): without a device the calls get past
+    validation and fail only at the HIP level."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L = wmc.lib()
+    S = wmc.Shape(1, 70000, 64, 64, 70000 * 64)
+    nb = 70000 * 64 * 4
+    ws = L.wmc_backward_workspace(S, 6, 3)
+    assert ws > 0 and L.wmc_solve_workspace(S) == nb
+    rc = L.wmc_solve(P(1 << 32), None, P(1 << 34), P(1 << 36), 6, 0.0, P(1 << 38), 3, None,
+                     P(1 << 40), nb, S, None)
+    assert rc in (wmc.WMC_EHIP, wmc.WMC_EUNSUPPORTED), L.wmc_last_error()
+    rc = L.wmc_backward(P(1 << 32), None, P(1 << 36), 6, 0.0, P(1 << 38), 3, P(1 << 42),
+                        P(1 << 44), None, P(1 << 46), P(1 << 48), ws, S, None)
+    assert rc in (wmc.WMC_EHIP, wmc.WMC_EUNSUPPORTED), L.wmc_last_error()
+
+
 def test_fault_injection_paths(wmc, monkeypatch):
     """WMC_FAULT_INJECT makes the library report a HIP failure from host code."""
     L = wmc.lib()
@@ -214,3 +234,22 @@ def test_default_checkpoint_period_policy():
     budget = W.KEEP_ALL_STATES_BYTES
     assert W.default_ckpt_every(4, budget // 4) == 1
     assert W.default_ckpt_every(4, budget // 4 + 1) == 2
+
+
+def test_binding_shape_checks_on_host(wmc):
+    """The binding's shape checks (run before any call into the library):
+    an array passed with one layout must have exactly that shape, and a
+    checkpoint buffer exactly the plane sets its solve stored."""
+    import torch
+    ref = torch.empty((2, 5, 7))
+    wmc.require_shape(None, ref.shape, "u0")
+    wmc.require_shape(torch.empty((2, 5, 7)), ref.shape, "u0")
+    for bad in [(1, 5, 7), (2, 4, 7), (2, 5, 8), (3, 5, 7)]:
+        with pytest.raises(ValueError, match="g_out has shape"):
+            wmc.require_shape(torch.empty(bad), ref.shape, "g_out")
+    assert wmc.checkpoint_sets(20, 5) == 4
+    assert wmc.checkpoint_sets(20, 2) == 10
+    assert wmc.checkpoint_sets(21, 5) == 5
+    assert wmc.checkpoint_sets(0, 5) == 1       # a solve of 0 steps still returns one set
+    with pytest.raises(ValueError):
+        wmc.checkpoint_sets(20, 0)

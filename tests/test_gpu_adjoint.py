@@ -159,11 +159,11 @@ def test_autograd_function(wmc):
     f = to_gpu(rng.uniform(0, 1, size=(3, 36, 50))).requires_grad_(True)
     target = to_gpu(rng.uniform(0, 1, size=(3, 36, 50)))
     lam = torch.tensor([0.5, 1.0, 2.0], device="cuda:0", requires_grad=True)
-    out = wmc.WMCSolve.apply(f, lam, 9)
+    c = 3  # ceil(sqrt(9)), passed explicitly (the default keeps every state)
+    out = wmc.WMCSolve.apply(f, lam, 9, 0.0, c)
     loss = ((out - target) ** 2).mean()
     loss.backward()
     # same numbers through the explicit binding
-    c = 3  # ceil(sqrt(9))
     uK, ck = wmc.solve(f.detach(), lam.detach(), 9, ckpt_every=c)
     assert torch.equal(uK, out.detach())
     g_f, _, g_lam = wmc.backward(2 * (uK - target) / uK.numel(), f.detach(), lam.detach(), 9, ck, c)
@@ -262,3 +262,36 @@ def test_rows_per_item_override(wmc, monkeypatch):
     got = wmc.backward(g, f, lam, 6, ck, 2)
     assert torch.equal(got[0], ref[0])
     assert torch.allclose(got[2], ref[2], rtol=1e-5, atol=0.0)
+
+
+def test_tall_image_checkpointed_solve_and_backward(wmc):
+    """An image taller than 65535 rows (1 x 70000 x 64) through the paths that
+    copy and accumulate whole plane sets: a zero-step solve (a copy), a
+    checkpointed solve, and the backward from those checkpoints (dL/df,
+    dL/dU^0 and dL/dlam), against the FP64 oracle with the GPU's selections
+    replayed, over the whole image."""
+    H, W, K, c = 70000, 64, 6, 3
+    rng = np.random.default_rng(70000)
+    f_np = rng.uniform(0, 1, size=(H, W))
+    u0_np = rng.uniform(0, 1, size=(H, W))
+    g_np = rng.standard_normal((H, W))
+    f, u0, g = to_gpu(f_np), to_gpu(u0_np), to_gpu(g_np)
+    lam = torch.tensor([2.5], device="cuda:0")
+    assert torch.equal(wmc.solve(f, lam, 0, u0=u0), u0)
+    uK, ck = wmc.solve(f, lam, K, u0=u0, ckpt_every=c)
+    g_f, g_u0, g_lam = wmc.backward(g, f, lam, K, ck, c, u0=u0)
+    maps, u_steps = gpu_maps(wmc, f, lam, K, u0=u0)
+    assert torch.equal(uK, u_steps[0])
+    # the checkpoints are the states U^0 and U^3 of the trajectory
+    assert torch.equal(ck[0, 0], u0)
+    res = oracle.solve_adjoint(g_np, f_np.astype(np.float32), 2.5, K,
+                               u0=u0_np.astype(np.float32), m_forced_all=maps[0])
+    assert rel(g_f[0].cpu().numpy(), res["gf"]) <= 1e-4
+    assert rel(g_u0[0].cpu().numpy(), res["gu0"]) <= 1e-4
+    assert abs(float(g_lam[0]) - res["glam"]) <= 1e-4 * abs(res["glam"])
+    # U^0 = f: dL/df includes the path through U^0 (a plane-set accumulate)
+    uK2, ck2 = wmc.solve(f, lam, K, ckpt_every=c)
+    g_f2, _, _ = wmc.backward(g, f, lam, K, ck2, c)
+    maps2, _ = gpu_maps(wmc, f, lam, K)
+    res2 = oracle.solve_adjoint(g_np, f_np.astype(np.float32), 2.5, K, m_forced_all=maps2[0])
+    assert rel(g_f2[0].cpu().numpy(), res2["gf"] + res2["gu0"]) <= 1e-4
