@@ -108,50 +108,81 @@ def test_backward_fixed_step_and_flow_mode(wmc):
     assert abs(float(g_lam[0]) - res["glam"]) <= 1e-4 * abs(res["glam"])
 
 
-def test_backward_vs_fp64_finite_differences(wmc):
-    """32x32 crops of the differentiable-layer workload as standalone images."""
-    noisy, clean = wmc_synth.c4(batch=2, side=512)
-    K, lam = 20, 1.0
-    crops = [(240, 240), (17, 301)]
-    rng = np.random.default_rng(3)
-    for b, (y0, x0) in enumerate(crops):
-        f64 = noisy[b, 0, y0:y0 + 32, x0:x0 + 32].astype(np.float64)
-        c64 = clean[b, 0, y0:y0 + 32, x0:x0 + 32].astype(np.float64)
-        f = to_gpu(f64)
-        lt = torch.tensor([lam], device="cuda:0")
-        uK, ck = wmc.solve(f, lt, K, ckpt_every=5)
-        g_out = 2.0 * (uK - to_gpu(c64)) / uK.numel()
-        g_f, _, g_lam = wmc.backward(g_out, f, lt, K, ck, 5)
-        g_f = g_f[0].cpu().numpy().astype(np.float64)
+def fd_crop_check(wmc, f64, c64, lam, K, rng, n_try=40):
+    """dL/df at n_try random pixels and dL/dlam of one standalone crop: the
+    GPU adjoint (checkpoints every ceil(sqrt(K))) against FP64 central
+    differences of the oracle's solve, skipping perturbations that change a
+    selection anywhere along the path."""
+    c = int(np.ceil(np.sqrt(K)))
+    f = to_gpu(f64)
+    lt = torch.tensor([lam], device="cuda:0")
+    uK, ck = wmc.solve(f, lt, K, ckpt_every=c)
+    g_out = 2.0 * (uK - to_gpu(c64)) / uK.numel()
+    g_f, _, g_lam = wmc.backward(g_out, f, lt, K, ck, c)
+    g_f = g_f[0].cpu().numpy().astype(np.float64)
 
-        def loss(ff, ll):
-            u = oracle.solve(ff, lam=ll, iters=K)
-            return float(((u - c64) ** 2).mean())
+    def loss(ff, ll):
+        u = oracle.solve(ff, lam=ll, iters=K)
+        return float(((u - c64) ** 2).mean())
 
-        def path_maps(ff):
-            u = ff.copy()
-            out = []
-            for _ in range(K):
-                u, m = oracle.step(u, ff, lam, return_argmin=True)
-                out.append(m)
-            return np.stack(out)
+    def path_maps(ff):
+        u = ff.copy()
+        out = []
+        for _ in range(K):
+            u, m = oracle.step(u, ff, lam, return_argmin=True)
+            out.append(m)
+        return np.stack(out)
 
-        h = 1e-6
-        checked, errs = 0, []
-        for _ in range(40):
-            y, x = int(rng.integers(32)), int(rng.integers(32))
-            fp, fm = f64.copy(), f64.copy()
-            fp[y, x] += h
-            fm[y, x] -= h
-            if not np.array_equal(path_maps(fp), path_maps(fm)):
-                continue
-            fd = (loss(fp, lam) - loss(fm, lam)) / (2 * h)
-            errs.append(abs(fd - g_f[y, x]) / max(abs(fd), 1e-3 * np.abs(g_f).max()))
-            checked += 1
-        assert checked >= 20
-        assert max(errs) <= 1e-4, max(errs)
-        fdl = (loss(f64, lam + h) - loss(f64, lam - h)) / (2 * h)
-        assert abs(fdl - float(g_lam[0])) <= 1e-4 * abs(fdl)
+    h = 1e-6
+    H, W = f64.shape
+    checked, errs = 0, []
+    for _ in range(n_try):
+        y, x = int(rng.integers(H)), int(rng.integers(W))
+        fp, fm = f64.copy(), f64.copy()
+        fp[y, x] += h
+        fm[y, x] -= h
+        if not np.array_equal(path_maps(fp), path_maps(fm)):
+            continue
+        fd = (loss(fp, lam) - loss(fm, lam)) / (2 * h)
+        errs.append(abs(fd - g_f[y, x]) / max(abs(fd), 1e-3 * np.abs(g_f).max()))
+        checked += 1
+    assert checked >= n_try // 2
+    assert max(errs) <= 1e-4, max(errs)
+    fdl = (loss(f64, lam + h) - loss(f64, lam - h)) / (2 * h)
+    assert abs(fdl - float(g_lam[0])) <= 1e-4 * abs(fdl)
+
+
+def c4_crops():
+    """The four 32x32 crops of the differentiable-layer workload: (240, 240)
+    of image 0 and three seeded ones on images 1..3."""
+    rng = np.random.default_rng(2020)
+    crops = [(0, 240, 240)]
+    for b in (1, 2, 3):
+        crops.append((b, int(rng.integers(0, 512 - 32)), int(rng.integers(0, 512 - 32))))
+    return crops
+
+
+@pytest.mark.parametrize("crop", range(4))
+def test_backward_vs_fp64_finite_differences(wmc, crop):
+    """32x32 crops of the differentiable-layer workload (lambda = 1, K = 20)
+    as standalone images."""
+    noisy, clean = wmc_synth.c4(batch=4, side=512)
+    b, y0, x0 = c4_crops()[crop]
+    f64 = noisy[b, 0, y0:y0 + 32, x0:x0 + 32].astype(np.float64)
+    c64 = clean[b, 0, y0:y0 + 32, x0:x0 + 32].astype(np.float64)
+    fd_crop_check(wmc, f64, c64, 1.0, 20, np.random.default_rng(3 + crop))
+
+
+@pytest.mark.parametrize("lam", [0.3, 2.5])
+def test_backward_vs_fp64_finite_differences_lambda(wmc, lam):
+    """The same finite-difference check away from lambda = 1, where the
+    default step 1/(1+lambda) differs from 1 - 1/(1+lambda), so a swapped
+    data-term factor or a wrong d(delta)/d(lambda) term would show."""
+    noisy, clean = wmc_synth.c4(batch=4, side=512)
+    b, y0, x0 = c4_crops()[1 if lam < 1 else 2]
+    f64 = noisy[b, 0, y0:y0 + 32, x0:x0 + 32].astype(np.float64)
+    c64 = clean[b, 0, y0:y0 + 32, x0:x0 + 32].astype(np.float64)
+    fd_crop_check(wmc, f64, c64, lam, 20, np.random.default_rng(int(lam * 10)))
 
 
 def test_autograd_function(wmc):
@@ -178,14 +209,14 @@ def test_autograd_function(wmc):
 
 def test_c4_batch_against_oracle(wmc):
     """The full differentiable-layer batch (16x1x512x512, K = 20, checkpoints
-    every 5): two images checked against the shadowed FP64 adjoint."""
+    every 5): every image checked against the shadowed FP64 adjoint."""
     noisy, clean = wmc_synth.c4()
     f = to_gpu(noisy[:, 0])
     lam = torch.ones(16, device="cuda:0")
     uK, ck = wmc.solve(f, lam, 20, ckpt_every=5)
     g_out = 2.0 * (uK - to_gpu(clean[:, 0])) / uK.numel()
     g_f, _, g_lam = wmc.backward(g_out, f, lam, 20, ck, 5)
-    for b in (0, 11):
+    for b in range(16):
         fb = f[b:b + 1]
         maps, _ = gpu_maps(wmc, fb, lam[b:b + 1], 20)
         res = oracle.solve_adjoint(g_out[b].cpu().numpy().astype(np.float64),

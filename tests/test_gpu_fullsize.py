@@ -1,12 +1,18 @@
 """The benchmark workload at full size (4096 x 4096, 200 iterations) in the
 launch configuration bench.py times: properties that hold at any size and
 oracle checks on sampled pixels."""
+import os
+import sys
+
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import wmc_synth
+
+sys.path.insert(0, os.path.dirname(__file__))
+from parity_bounds import TAU, TOL  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -52,9 +58,56 @@ def test_sampled_pixels_against_oracle(setup):
             if abs(want - got[y, x]) > 1e-5:
                 y0, y1 = max(0, y - T), min(4096, y + T + 1)
                 x0, x1 = max(0, x - T), min(4096, x + T + 1)
-                assert oracle.near_tie_mask(src[y0:y1, x0:x1], 1e-4).any(), (y, x)
+                assert oracle.near_tie_mask(src[y0:y1, x0:x1], TAU).any(), (y, x)
                 flips += 1
     assert flips <= 3
+
+
+def test_full_plane_step_against_oracle(setup):
+    """One Jacobi update of the whole 4096^2 plane from U = f, every pixel
+    against the FP64 oracle: a pixel off by more than 1e-5 passes only as the
+    update through a candidate within TAU (x12 units) of the minimum."""
+    W, noisy, f, lam, tuning = setup
+    f64 = noisy[0].astype(np.float64)
+    u1 = W.step(f, f, lam)[0].cpu().numpy().astype(np.float64)
+    ref = oracle.step(f64, f64, 1.0)
+    bad = np.abs(u1 - ref) > TOL
+    nb = int(bad.sum())
+    if nb:
+        S = oracle.candidates(f64)[bad]
+        mag = np.abs(S)
+        close = mag <= mag.min(axis=1, keepdims=True) + TAU
+        upd = f64[bad][:, None] + 0.5 * S / 12.0   # U = f, delta = 1/2, lam = 1
+        ok = np.any(close & (np.abs(upd - u1[bad][:, None]) <= TOL), axis=1)
+        assert ok.all(), f"{int((~ok).sum())} pixels off outside near ties"
+    assert nb <= 1e-4 * f64.size
+
+
+def test_full_plane_fused_block_shadow(setup):
+    """The first fused launch of the benchmark solve (T sweeps from U = f) over
+    the whole plane, under the shadow protocol: at every sweep each selection
+    the GPU made must be within TAU of the minimum magnitude of the oracle's
+    candidates on the shadow state, and the oracle, replaying those
+    selections, must end within 1e-5 of the fused output everywhere."""
+    W, noisy, f, lam, tuning = setup
+    T = tuning["tsteps"]
+    f64 = noisy[0].astype(np.float64)
+    uT = W.solve(f, lam, T, tuning=tuning)[0]
+    u = f.clone()
+    maps = []
+    for _ in range(T):
+        u, m = W.step(u, f, lam, return_argmin=True)
+        maps.append(m[0].cpu().numpy().astype(np.int64))
+    assert torch.equal(u[0], uT)   # the fused launch is its T single sweeps
+    sh = f64.copy()
+    for t in range(T):
+        S = oracle.candidates(sh)
+        mag = np.abs(S)
+        chosen = np.take_along_axis(mag, maps[t][..., None], axis=2)[..., 0]
+        assert (chosen <= mag.min(axis=2) + TAU).all(), f"disallowed selection at sweep {t}"
+        del S, mag, chosen
+        sh = oracle.step(sh, f64, 1.0, m_forced=maps[t])
+    assert np.abs(uT.cpu().numpy().astype(np.float64) - sh).max() <= TOL
 
 
 def test_denoising_quality(setup):
@@ -95,13 +148,13 @@ def test_planes_beyond_2_pow_30_elements():
             ref = oracle.step_window(cu, cf, y - y0, x - x0, k, lam=float(lam[p]))
             val = float(got[p, y, x])
             if abs(val - ref) > 1e-5:  # only through a near tie of the selection
-                assert k == 1 and oracle.near_tie_mask(cu, 1e-4)[y - y0, x - x0], (p, y, x, k)
+                assert k == 1 and oracle.near_tie_mask(cu, TAU)[y - y0, x - x0], (p, y, x, k)
         y0, y1 = max(0, y - 1), min(H, y + 2)
         x0, x1 = max(0, x - 1), min(Wd, x + 2)
         cu = u[p, y0:y1, x0:x1].cpu().numpy().astype(np.float64)
         hr = oracle.compute(cu)[y - y0, x - x0]
         hv = float(h[p, y, x])
         if abs(hv - hr) > 1e-5:
-            assert oracle.near_tie_mask(cu, 1e-4)[y - y0, x - x0], (p, y, x)
+            assert oracle.near_tie_mask(cu, TAU)[y - y0, x - x0], (p, y, x)
     del u, f, u1, h, u3
     torch.cuda.empty_cache()

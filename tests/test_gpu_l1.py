@@ -1,10 +1,16 @@
 """The l1-fidelity primal-dual solver of Sec. 5.3 on the GPU against the oracle."""
+import os
+import sys
+
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import wmc_synth
+
+sys.path.insert(0, os.path.dirname(__file__))
+from parity_bounds import TAU  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +41,7 @@ def test_l1_one_step_parity(wmc, shape):
     du = np.abs(u1.cpu().numpy() - ru)
     bad = du > 1e-5
     if bad.any():  # only through a near tie of the selection
-        assert oracle.near_tie_mask(U.astype(np.float32).astype(np.float64), 1e-4)[bad].all()
+        assert oracle.near_tie_mask(U.astype(np.float32).astype(np.float64), TAU)[bad].all()
 
 
 @pytest.mark.parametrize("c,t,r", [(1, 1, 8), (2, 3, 16), (4, 2, 32), (2, 8, 5), (1, 6, 64)])
@@ -77,7 +83,7 @@ def test_l1_multi_step_parity_and_robustness(wmc):
         S = oracle.candidates(U)
         mag = np.abs(S)
         gm = np.take_along_axis(mag, m.astype(np.int64)[..., None], axis=2)[..., 0]
-        assert (gm <= mag.min(axis=2) + 1e-4).all(), t
+        assert (gm <= mag.min(axis=2) + TAU).all(), t
         U, D = oracle.l1_step(U, D, f64, lam, alpha, m_forced=m)
         u, d = wmc.solve_l1(fg, lam, alpha, 1, u0=u, d0=d)
     assert np.abs(u.cpu().numpy() - U).max() <= 1e-4

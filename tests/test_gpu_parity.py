@@ -9,6 +9,9 @@ differently.  A pixel whose value differs from the oracle's by more than the
 tolerance passes only if the GPU value is the update of a candidate within
 TAU (x12 units) of the minimum magnitude, and such pixels are counted.
 """
+import os
+import sys
+
 import numpy as np
 import pytest
 import torch
@@ -16,10 +19,11 @@ import torch
 import oracle
 import wmc_synth
 
+sys.path.insert(0, os.path.dirname(__file__))
+from parity_bounds import TAU, TOL  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-5
-TAU = 1e-4
 
 
 @pytest.fixture(scope="module")
