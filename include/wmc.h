@@ -136,6 +136,28 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
 int wmc_solve_tuning(const float* f, const float* u0, const float* lam, float dt, void* ws,
                      size_t ws_bytes, wmc_shape s, wmc_tuning* out, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * wmc_solve_noalloc -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same solve as wmc_solve without checkpoints (same kernels,
+ * bitwise the same result), with its ping-pong state in a static device
+ * array of WMC_NOALLOC_SCRATCH_BYTES that the library holds on every device
+ * it runs on until the process ends, instead of a caller workspace.  It calls
+ * no hipMalloc / hipFree, captures no graph and runs no tuning search: the
+ * launch shape is `tune` if complete, else the autotuner's cached choice for
+ * this shape (wmc_solve_tuning), else the default.  Arguments as for
+ * wmc_solve; the caller owns f, u0, u_out and lam.
+ * Errors: WMC_EINVAL (as wmc_solve, and when iters >= 2 and one plane set,
+ * wmc_set_stride(s) floats, exceeds WMC_NOALLOC_SCRATCH_BYTES; nothing is
+ * enqueued then), WMC_EHIP.  Every call on a device shares that device's
+ * array: calls that overlap on one device (other streams or threads) race
+ * and give wrong results.  Each launch writes the whole plane set it hands
+ * to the next, so the array needs no clearing between calls.
+ * ------------------------------------------------------------------------- */
+#define WMC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int wmc_solve_noalloc(const float* f, const float* u0, float* u_out, const float* lam, int iters,
+                      float dt, const wmc_tuning* tune, wmc_shape s, void* stream);
+
 /* Bytes of workspace wmc_solve_l1 needs (two extra plane sets). */
 size_t wmc_l1_workspace(wmc_shape s);
 

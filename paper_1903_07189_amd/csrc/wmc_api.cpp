@@ -805,6 +805,21 @@ int tune_single(int dev, const wmc_shape& s, const float* src, const float* f, c
     return get_tuning(single_tune_key(dev, s, mode), deflt, search, t);
 }
 
+// The tuning tune_single would return, without searching: the cached entry of
+// this shape, else the default (no device work, no allocation).
+Tuned cached_single_tuning(int dev, const wmc_shape& s, const float* src, const float* f,
+                           const float* ws) {
+    const int mode = f ? kModeData : kModeFlow;
+    const int C0 = std::min(2, vec_cols({src, f, ws}, s.ld, s.n > 1 ? s.ps : 0));
+    Tuned t{C0, 3, default_rows(s.n, s.h, s.w, C0, 3, dev, mode)};
+    if (tune_mode() == TuneMode::Off) return t;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file();
+    auto it = g_tune.find(single_tune_key(dev, s, mode));
+    if (it != g_tune.end()) t = it->second;
+    return t;
+}
+
 std::string batch_tune_key(int dev, const std::vector<BatchImg>& imgs, int mode) {
     int64_t px = 0;
     std::vector<int64_t> ws;
@@ -1014,7 +1029,23 @@ int wmc_step(const float* u, const float* f, float* u_out, const float* lam, flo
 int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, int iters,
               float dt, float* ckpt, int ckpt_every, const wmc_tuning* tune, void* ws,
               size_t ws_bytes, wmc_shape s, void* stream) {
+    return wmc::solve_impl(f, u0, u_out, lam, iters, dt, ckpt, ckpt_every, tune, ws, ws_bytes, s,
+                           stream, false);
+}
+
+}  // extern "C"
+
+int wmc::report_error(int code, const std::string& msg) { return fail(code, msg); }
+
+// wmc_solve's body.  With `noalloc` (the static-scratch entry point) it takes
+// no checkpoints, runs no tuning search (a complete `tune`, else the cached
+// tuning of this shape, else the default), captures no graph and reports a
+// workspace that is too small as WMC_EINVAL: the scratch has a fixed size.
+int wmc::solve_impl(const float* f, const float* u0, float* u_out, const float* lam, int iters,
+                    float dt, float* ckpt, int ckpt_every, const wmc_tuning* tune, void* ws,
+                    size_t ws_bytes, wmc_shape s, void* stream, bool noalloc) {
     g_err.clear();
+    if (noalloc && ckpt) return fail(WMC_EINVAL, "wmc_solve_noalloc: no checkpoints");
     int rc = check_shape(s);
     if (rc) return rc;
     if (!u_out) return fail(WMC_EINVAL, "wmc_solve: null u_out");
@@ -1026,6 +1057,10 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
     const int64_t ext = extent_elems(s);
     const int64_t stride = set_stride_elems(s);
     const size_t need = wmc_solve_workspace(s);
+    if (noalloc && iters >= 2 && need > ws_bytes)
+        return fail(WMC_EINVAL, "wmc_solve_noalloc: one plane set (" + std::to_string(need) +
+                                    " bytes) exceeds the static scratch (" +
+                                    std::to_string(ws_bytes) + " bytes)");
     if (iters >= 2 && (!ws || ws_bytes < need))
         return fail(WMC_ENOMEM, "wmc_solve: workspace smaller than wmc_solve_workspace()");
     const float* src0 = u0 ? u0 : f;
@@ -1051,6 +1086,9 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
     bool graph = true;
     if (tuning_complete(tune)) {
         rc = resolve_tuning(tune, Tuned{2, 4, 64}, &t, &graph);
+    } else if (noalloc) {
+        rc = resolve_tuning(tune, cached_single_tuning(dev, s, src0, f, static_cast<float*>(ws)),
+                            &t, &graph);
     } else {
         Tuned auto_t{};
         // with a workspace the candidates read U from u_out (contents
@@ -1088,9 +1126,9 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
         }
         return WMC_OK;
     };
-    if (!graph) {
-        PlanEntry scratch;
-        return enqueue(st, scratch);
+    if (!graph || noalloc) {
+        PlanEntry direct;
+        return enqueue(st, direct);
     }
     std::string key = "solve|";
     key_add(key, s);
@@ -1108,6 +1146,8 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
     auto prepare = [](PlanEntry&) { return WMC_OK; };
     return run_plan(key, dev, st, true, prepare, enqueue);
 }
+
+extern "C" {
 
 size_t wmc_l1_workspace(wmc_shape s) {
     if (check_shape(s)) return 0;

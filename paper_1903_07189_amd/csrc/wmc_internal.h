@@ -6,6 +6,10 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+
+#include "wmc.h"
+
 namespace wmc {
 
 // ---------------------------------------------------------------------------
@@ -158,5 +162,15 @@ hipError_t launch_stream3d(const float* u, const float* f, float* out, const flo
 // Auxiliary kernels (wmc_aux.hip).
 hipError_t launch_fd(const float* u, float* out, int64_t n, int64_t h, int64_t w, int64_t ld,
                      int64_t ps, float dt, float eps, bool flow, hipStream_t st);
+
+// Sets the calling thread's wmc_last_error() message and returns `code`.
+int report_error(int code, const std::string& msg);
+
+// Host side of wmc_solve (wmc_api.cpp).  `noalloc`: the static-scratch entry
+// point's mode -- no checkpoints, no tuning search, no graph, and `ws` is the
+// scratch of ws_bytes (WMC_EINVAL if one plane set does not fit).
+int solve_impl(const float* f, const float* u0, float* u_out, const float* lam, int iters,
+               float dt, float* ckpt, int ckpt_every, const wmc_tuning* tune, void* ws,
+               size_t ws_bytes, wmc_shape s, void* stream, bool noalloc);
 
 }  // namespace wmc

@@ -56,7 +56,7 @@ class Tuning(ctypes.Structure):
 
 _lib = None
 EXPORTS = ["wmc_compute", "wmc_step", "wmc_solve_workspace", "wmc_set_stride",
-           "wmc_num_checkpoints", "wmc_solve", "wmc_solve_tuning", "wmc_l1_workspace",
+           "wmc_num_checkpoints", "wmc_solve", "wmc_solve_noalloc", "wmc_solve_tuning", "wmc_l1_workspace",
            "wmc_solve_l1", "wmc_fd_compute", "wmc_fd_flow", "wmc_layer_workspace",
            "wmc_layer_forward", "wmc_layer_backward", "wmc_workspace_bytes",
            "wmc3_compute", "wmc3_step", "wmc3_solve_workspace", "wmc3_solve",
@@ -83,6 +83,7 @@ def lib():
     L.wmc_num_checkpoints.argtypes = [I, I]
     L.wmc_num_checkpoints.restype = I64
     L.wmc_solve.argtypes = [P, P, P, P, I, F, P, I, ctypes.POINTER(Tuning), P, SZ, Shape, P]
+    L.wmc_solve_noalloc.argtypes = [P, P, P, P, I, F, ctypes.POINTER(Tuning), Shape, P]
     L.wmc_solve_tuning.argtypes = [P, P, P, F, P, SZ, Shape, ctypes.POINTER(Tuning), P]
     L.wmc_l1_workspace.argtypes = [Shape]
     L.wmc_l1_workspace.restype = SZ
@@ -113,7 +114,8 @@ def lib():
     L.wmc_last_error.restype = ctypes.c_char_p
     L.wmc_release.argtypes = []
     L.wmc_release.restype = None
-    for name in ("wmc_compute", "wmc_step", "wmc_solve", "wmc_solve_tuning", "wmc_solve_l1",
+    for name in ("wmc_compute", "wmc_step", "wmc_solve", "wmc_solve_noalloc", "wmc_solve_tuning",
+                 "wmc_solve_l1",
                  "wmc_fd_compute", "wmc_fd_flow", "wmc_layer_forward", "wmc_layer_backward",
                  "wmc3_compute", "wmc3_step", "wmc3_solve",
                  "wmc_solve_batched",
@@ -260,6 +262,30 @@ def solve(f: torch.Tensor | None, lam=1.0, iters: int = 1, dt: float = 0.0,
     if squeeze:
         out = out[0]
     return (out, ck) if ckpt_every else out
+
+
+def solve_noalloc(f: torch.Tensor | None, lam, iters: int, out: torch.Tensor, dt: float = 0.0,
+                  u0: torch.Tensor | None = None, tuning=None) -> torch.Tensor:
+    """solve() through wmc_solve_noalloc: no workspace and no checkpoints; the
+    library keeps the intermediate state in its static device scratch.  The
+    caller passes the output tensor `out` (f's shape), so nothing here
+    allocates device memory as long as lam is a device tensor of one value per
+    plane."""
+    ref = f if f is not None else u0
+    if ref is None:
+        raise ValueError("need f or u0")
+    for name, t in (("f", f), ("u0", u0), ("out", out)):
+        if t is not None and (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    require_shape(u0, ref.shape, "u0")
+    require_shape(out, ref.shape, "out")
+    r3 = ref if ref.dim() == 3 else ref.unsqueeze(0)
+    s = shape_of(r3)
+    lt = _lam_tensor(lam, r3.shape[0], ref.device) if f is not None else None
+    tn = _tuning(tuning)
+    check(lib().wmc_solve_noalloc(_ptr(f), _ptr(u0), _ptr(out), _ptr(lt), int(iters), float(dt),
+                                  ctypes.byref(tn) if tn else None, s, _stream()))
+    return out
 
 
 def solve_l1(f: torch.Tensor, lam=1.0, alpha: float = 0.05, iters: int = 1, dt: float = 0.0,
