@@ -80,6 +80,19 @@ def read_traffic(tuning, side):
         return None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo, as lscpu reports it)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(side: int, sample_iters: int):
     """The FP64 oracle (single thread, pinned to one core) on the same input."""
     import numpy as np
@@ -96,7 +109,8 @@ def cpu_baseline(side: int, sample_iters: int):
     oracle.solve(f, lam=1.0, iters=sample_iters)
     dt = time.perf_counter() - t0
     out = {"value": round(side * side * sample_iters / dt / 1e9, 6), "unit": "Gpixel-iter/s",
-           "cores": 1, "kind": "oracle",
+           "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
+           "host_logical_cpus": len(cpus) if cpus else os.cpu_count(),
            "sample": f"{side}x{side} input, {sample_iters} of the 200 iterations "
                      f"({dt:.1f} s, FP64, one thread)"}
     # two more bounded samples: the 256 x 256 parity image in full (50
@@ -350,9 +364,9 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side, only=None):
     def want(name):
         return only is None or name in only
     if want("copy_ceiling"):
-        ex.update(_copy_ceiling(torch, f, stream))
+        ex.update(_copy_ceiling(torch, wmc, f, stream))
     if want("step_T1_4096") or want("step_T1_8192"):
-        ex.update(_steps_t1(torch, wmc, f, lam, stream, side, want))
+        ex.update(_steps_t1(torch, wmc, f, lam, stream, side, want, ex))
     if want("compute_4096"):
         ms, hid = timed_device(lambda: wmc.compute(f), 20, stream, torch)
         ms /= 20
@@ -420,31 +434,41 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side, only=None):
     return ex
 
 
-def _copy_ceiling(torch, f, stream):
-    ex = {}
-    # device copy ceiling: 1 GiB read + 1 GiB written
-    a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=f.device).fill_(1.0)
-    b = torch.empty_like(a)
-    b.copy_(a)
-    ms = timed(lambda: b.copy_(a), 5, stream, torch) / 5
-    ex["copy_ceiling"] = {"gbs": round(2 * a.numel() * 4 / (ms * 1e-3) / 1e9, 1),
-                          "note": "torch copy of 1 GiB (read + write)"}
-    del a, b
-    # the single update's access pattern (two planes read, one written) as a
-    # torch element-wise add over 8192^2 fp32 planes: 768 MiB, beyond the
-    # Infinity Cache
-    a = torch.rand((8192, 8192), device=f.device)
+def probe_ceiling(torch, wmc, side, stream, reps=20):
+    """Achievable streaming bandwidth (GB/s) from the library's probe kernel
+    (wmc_bw_probe) over side^2 fp32 planes: copy (one read, one write) and
+    add o = a + b (two reads, one write: the single update's pattern), with
+    plain and with non-temporal accesses."""
+    n = side * side
+    a = torch.rand(n, device="cuda:0")
     b = torch.rand_like(a)
     o = torch.empty_like(a)
-    torch.add(a, b, out=o)
-    ms = timed(lambda: torch.add(a, b, out=o), 10, stream, torch) / 10
-    ex["add_ceiling_8192"] = {"gbs": round(3 * a.numel() * 4 / (ms * 1e-3) / 1e9, 1),
-                              "note": "torch add o = a + b over 8192^2 fp32 (two reads, one write)"}
+    out = {}
+    for op in ("copy", "add"):
+        for nt in (False, True):
+            def run():
+                wmc.bw_probe(a, o, b if op == "add" else None, nontemporal=nt)
+            run()
+            ms = timed(run, reps, stream, torch) / reps
+            planes = 3 if op == "add" else 2
+            out[f"{op}{'_nt' if nt else ''}"] = round(planes * n * 4 / (ms * 1e-3) / 1e9, 1)
     del a, b, o
+    return out
+
+
+def _copy_ceiling(torch, wmc, f, stream):
+    ex = {}
+    # the library's streaming probe: 8192^2 planes (256 MiB each; the add's
+    # 768 MiB exceed the 256 MB Infinity Cache) and 4096^2 (cache-resident)
+    p8 = probe_ceiling(torch, wmc, 8192, stream)
+    p4 = probe_ceiling(torch, wmc, 4096, stream)
+    ex["probe_8192"] = dict(p8, note="wmc_bw_probe GB/s: copy and o = a + b over 8192^2 fp32, "
+                                     "plain and non-temporal")
+    ex["probe_4096"] = dict(p4, note="the same over 4096^2 (working set inside the Infinity Cache)")
     return ex
 
 
-def _steps_t1(torch, wmc, f, lam, stream, side, want):
+def _steps_t1(torch, wmc, f, lam, stream, side, want, probes):
     ex = {}
     # plain single-update kernel (one launch per iteration, graph-replayed); the
     # launch shape is picked from a few candidates, best reported
@@ -469,12 +493,19 @@ def _steps_t1(torch, wmc, f, lam, stream, side, want):
                               "gpx_per_s": round(gbs / BYTES_PER_PX_PASS, 2), "tuning": t1,
                               "note": "warm: the 192 MiB working set fits the 256 MB Infinity "
                                       "Cache"}
+        if "probe_4096" in probes:
+            ex["step_T1_4096"]["probe_add_frac"] = round(gbs / probes["probe_4096"]["add"], 4)
     if want("step_T1_8192"):
         # 8192^2 control, larger than the Infinity Cache
         g = torch.rand((1, 8192, 8192), device=f.device)
         gbs, t1 = t1_gbs(g, 8192, 20, [(4, 2), (4, 3), (4, 4), (4, 8), (2, 4), (2, 14), (4, 12)])
         ex["step_T1_8192"] = {"gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                              "tuning": t1}
+                              "tuning": t1,
+                              "note": "768 MiB working set, beyond the Infinity Cache"}
+        if "probe_8192" in probes:
+            p8 = probes["probe_8192"]
+            ex["step_T1_8192"]["probe_add_frac"] = round(gbs / p8["add"], 4)
+            ex["step_T1_8192"]["probe_add_nt_frac"] = round(gbs / p8["add_nt"], 4)
         del g
     return ex
 

@@ -330,6 +330,21 @@ enum {
 };
 size_t wmc_workspace_bytes(int op, wmc_shape s, int iters, int ckpt_every);
 
+/* ---------------------------------------------------------------------------
+ * wmc_bw_probe -- a measurement aid, no part of the method: the streaming
+ * bandwidth the device achieves for the access pattern of an update, as the
+ * ceiling the update kernels are judged against.  op WMC_PROBE_COPY: o = a
+ * (one read, one write per float); WMC_PROBE_ADD: o = a + b (two reads, one
+ * write, the single update's pattern).  flags: WMC_PROBE_NONTEMPORAL makes
+ * every load and store non-temporal.  n floats, a positive multiple of 4;
+ * a, b, o device pointers, 16-byte aligned, o not overlapping a or b (b
+ * unused for a copy).  WMC_EINVAL on bad arguments (nothing enqueued).
+ * ------------------------------------------------------------------------- */
+enum { WMC_PROBE_COPY = 0, WMC_PROBE_ADD = 1 };
+enum { WMC_PROBE_NONTEMPORAL = 1 };
+int wmc_bw_probe(int op, const float* a, const float* b, float* o, int64_t n, int flags,
+                 void* stream);
+
 /* Checks on the current device that the wavefront lane shifts the kernels
  * rely on move data as expected; returns WMC_OK or WMC_EHIP/WMC_EUNSUPPORTED.
  * Synchronises the default stream. */

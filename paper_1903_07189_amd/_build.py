@@ -16,7 +16,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libwmc.so")
 
 SOURCES = ["wmc_stream.hip", "wmc_adjoint.hip", "wmc_aux.hip", "wmc_layer.hip", "wmc_3d.hip",
-           "wmc_noalloc.hip", "wmc_api.cpp"]
+           "wmc_noalloc.hip", "wmc_probe.hip", "wmc_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

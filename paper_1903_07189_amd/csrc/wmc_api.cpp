@@ -1822,6 +1822,27 @@ int wmc_fd_flow(const float* u0, float* u_out, int iters, float dt, float eps, v
     return WMC_OK;
 }
 
+int wmc_bw_probe(int op, const float* a, const float* b, float* o, int64_t n, int flags,
+                 void* stream) {
+    g_err.clear();
+    if (op != WMC_PROBE_COPY && op != WMC_PROBE_ADD) return fail(WMC_EINVAL, "wmc_bw_probe: op");
+    if (flags & ~WMC_PROBE_NONTEMPORAL) return fail(WMC_EINVAL, "wmc_bw_probe: unknown flags");
+    if (n <= 0 || n % 4) return fail(WMC_EINVAL, "wmc_bw_probe: n must be a positive multiple of 4");
+    if (!a || !o || (op == WMC_PROBE_ADD && !b)) return fail(WMC_EINVAL, "wmc_bw_probe: null pointer");
+    for (const void* p : {static_cast<const void*>(a), static_cast<const void*>(b),
+                          static_cast<const void*>(o)})
+        if (reinterpret_cast<uintptr_t>(p) % 16)
+            return fail(WMC_EINVAL, "wmc_bw_probe: pointers must be 16-byte aligned");
+    const Range ro = range_of(o, n, 4);
+    if (overlaps(ro, range_of(a, n, 4)) || (op == WMC_PROBE_ADD && overlaps(ro, range_of(b, n, 4))))
+        return fail(WMC_EINVAL, "wmc_bw_probe: o overlaps an input");
+    int rc = check_device(nullptr);
+    if (rc) return rc;
+    const hipError_t e = launch_bw_probe(op == WMC_PROBE_ADD, (flags & WMC_PROBE_NONTEMPORAL) != 0,
+                                         a, b, o, n, as_stream(stream));
+    return e == hipSuccess ? WMC_OK : hip_fail(e, "wmc_bw_probe launch");
+}
+
 int wmc_selftest(void) {
     g_err.clear();
     int dev;

@@ -163,6 +163,11 @@ hipError_t launch_stream3d(const float* u, const float* f, float* out, const flo
 hipError_t launch_fd(const float* u, float* out, int64_t n, int64_t h, int64_t w, int64_t ld,
                      int64_t ps, float dt, float eps, bool flow, hipStream_t st);
 
+// Streaming bandwidth probe (wmc_probe.hip): o = a, or o = a + b with `add`,
+// over n floats (n a multiple of 4, 16-byte aligned); `nt` = non-temporal.
+hipError_t launch_bw_probe(bool add, bool nt, const float* a, const float* b, float* o,
+                           int64_t n, hipStream_t st);
+
 // Sets the calling thread's wmc_last_error() message and returns `code`.
 int report_error(int code, const std::string& msg);
 

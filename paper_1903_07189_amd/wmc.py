@@ -61,7 +61,7 @@ EXPORTS = ["wmc_compute", "wmc_step", "wmc_solve_workspace", "wmc_set_stride",
            "wmc_layer_forward", "wmc_layer_backward", "wmc_workspace_bytes",
            "wmc3_compute", "wmc3_step", "wmc3_solve_workspace", "wmc3_solve",
            "wmc_batched_workspace", "wmc_solve_batched", "wmc_autotune", "wmc_backward_workspace",
-           "wmc_backward", "wmc_selftest", "wmc_last_error", "wmc_release"]
+           "wmc_backward", "wmc_bw_probe", "wmc_selftest", "wmc_last_error", "wmc_release"]
 
 
 def lib():
@@ -109,6 +109,7 @@ def lib():
     L.wmc_backward_workspace.argtypes = [Shape, I, I]
     L.wmc_backward_workspace.restype = SZ
     L.wmc_backward.argtypes = [P, P, P, I, F, P, I, P, P, P, P, P, SZ, Shape, P]
+    L.wmc_bw_probe.argtypes = [I, P, P, P, I64, I, P]
     L.wmc_selftest.argtypes = []
     L.wmc_last_error.argtypes = []
     L.wmc_last_error.restype = ctypes.c_char_p
@@ -120,7 +121,7 @@ def lib():
                  "wmc3_compute", "wmc3_step", "wmc3_solve",
                  "wmc_solve_batched",
                  "wmc_autotune",
-                 "wmc_backward", "wmc_selftest"):
+                 "wmc_backward", "wmc_bw_probe", "wmc_selftest"):
         getattr(L, name).restype = I
     _lib = L
     return L
@@ -588,6 +589,17 @@ def autotune(fs, iters: int = 100):
     check(L.wmc_autotune(arr, len(fs), int(iters), ctypes.byref(t), _ptr(ws), ws.numel() * 4,
                          _stream()))
     return {"cols": t.cols, "tsteps": t.tsteps, "seg_rows": t.seg_rows, "use_graph": t.use_graph}
+
+
+def bw_probe(a: torch.Tensor, o: torch.Tensor, b: torch.Tensor | None = None,
+             nontemporal: bool = False) -> None:
+    """Streaming bandwidth probe (measurement aid): o = a, or o = a + b."""
+    for t in (a, b, o):
+        if t is not None and (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()
+                              or t.numel() != a.numel()):
+            raise ValueError("bw_probe takes contiguous float32 CUDA tensors of one size")
+    check(lib().wmc_bw_probe(1 if b is not None else 0, _ptr(a), _ptr(b), _ptr(o), a.numel(),
+                             1 if nontemporal else 0, _stream()))
 
 
 def selftest():

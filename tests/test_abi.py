@@ -253,3 +253,19 @@ def test_binding_shape_checks_on_host(wmc):
     assert wmc.checkpoint_sets(0, 5) == 1       # a solve of 0 steps still returns one set
     with pytest.raises(ValueError):
         wmc.checkpoint_sets(20, 0)
+
+
+def test_bw_probe_validation(wmc):
+    """The bandwidth probe rejects bad arguments on the host, before any HIP
+    call."""
+    L = wmc.lib()
+    A, B, O = P(1 << 40), P(1 << 41), P(1 << 42)
+    assert L.wmc_bw_probe(2, A, B, O, 1024, 0, None) == wmc.WMC_EINVAL
+    assert L.wmc_bw_probe(0, A, None, O, 1024, 4, None) == wmc.WMC_EINVAL
+    assert L.wmc_bw_probe(0, A, None, O, 1022, 0, None) == wmc.WMC_EINVAL
+    assert L.wmc_bw_probe(0, A, None, O, 0, 0, None) == wmc.WMC_EINVAL
+    assert L.wmc_bw_probe(1, A, None, O, 1024, 0, None) == wmc.WMC_EINVAL
+    assert L.wmc_bw_probe(0, P((1 << 40) + 4), None, O, 1024, 0, None) == wmc.WMC_EINVAL
+    assert "aligned" in L.wmc_last_error().decode()
+    assert L.wmc_bw_probe(1, A, B, P((1 << 40) + 1024), 1024, 1, None) == wmc.WMC_EINVAL
+    assert "overlaps" in L.wmc_last_error().decode()
