@@ -254,6 +254,8 @@ def main():
     ap.add_argument("--train-only", type=int, default=0, metavar="N",
                     help="only run N training steps of the differentiable 16 x 512^2, K = 20 "
                          "solve (profiling runs)")
+    ap.add_argument("--train-ckpt", type=int, default=5, metavar="C",
+                    help="checkpoint period of --train-only (1: every state kept)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -282,10 +284,11 @@ def main():
 
     wmc.selftest()
     if args.train_only:
-        step, _ = train_step_fn(torch, wmc, wmc_synth, dev)
+        step, _ = train_step_fn(torch, wmc, wmc_synth, dev, args.train_ckpt)
         step()
         ms = timed(step, args.train_only, stream, torch) / args.train_only
-        print(json.dumps({"workload": "16 x 512^2 K=20 training step", "ms": round(ms, 4)}))
+        print(json.dumps({"workload": "16 x 512^2 K=20 training step", "ckpt_every": args.train_ckpt,
+                          "ms": round(ms, 4)}))
         return
     side, iters = args.side, args.iters
     noisy, _ = wmc_synth.c2(side=side)
