@@ -168,9 +168,16 @@ void split_run(int len, int T, std::vector<int>& out) {
 // strips)), R = ceil(h / nseg) -- the smallest k whose R is at least
 // max(8, 4T) rows (segment overlap costs T rows per sweep depth).  slots =
 // resident waves of this kernel variant (occupancy API) times the CUs.
-int64_t resident_waves(int dev, int C, int T, int mode, bool traj = false) {
+// Whether a launch over planes w columns wide takes the vector-only build
+// (see vector_only), assuming aligned rows, the usual case.
+bool likely_vector_only(int64_t w, int C, int T) {
+    return strip_count((int)w, C, T) >= 2 && (w - 64 * C) % C == 0;
+}
+
+int64_t resident_waves(int dev, int C, int T, int mode, bool traj = false, int64_t w = 0) {
     int per_cu = traj ? stream_traj_blocks_per_cu(C, T, mode)
-                      : stream_single_blocks_per_cu(C, T, mode, false);
+                      : stream_single_blocks_per_cu(C, T, mode, false,
+                                                    w > 0 && likely_vector_only(w, C, T));
     if (per_cu <= 0) per_cu = 1;
     return (int64_t)num_cu(dev) * per_cu * 4;  // 4 waves per 256-thread block
 }
@@ -184,7 +191,7 @@ int rows_for_rounds(int64_t planes, int64_t h, int64_t w, int C, int T, int64_t 
 
 int default_rows(int64_t planes, int64_t h, int64_t w, int C, int T, int dev, int mode,
                  bool traj = false) {
-    const int64_t slots = resident_waves(dev, C, T, mode, traj);
+    const int64_t slots = resident_waves(dev, C, T, mode, traj, w);
     const int64_t rmin = std::min<int64_t>(h, std::max<int64_t>(8, 4 * (int64_t)T));
     for (int k = 1; k <= 64; ++k) {
         const int R = rows_for_rounds(planes, h, w, C, T, slots, k);
@@ -198,7 +205,7 @@ int default_rows(int64_t planes, int64_t h, int64_t w, int C, int T, int dev, in
 // and two plain ones.
 std::vector<int> candidate_rows(int64_t planes, int64_t h, int64_t w, int C, int T, int dev,
                                 int mode) {
-    const int64_t slots = resident_waves(dev, C, T, mode);
+    const int64_t slots = resident_waves(dev, C, T, mode, false, w);
     std::vector<int> out;
     auto add = [&](int R) {
         if (R < 1 || R > 512) return;
@@ -1108,7 +1115,8 @@ int wmc::solve_impl(const float* f, const float* u0, float* u_out, const float* 
         t.R = default_rows(s.n, s.h, s.w, t.C, t.T, dev, mode, true);
     } else if (nck && t.T >= 2 && t.T <= kTrajMaxT && !tuning_complete(tune) &&
                stream_traj_blocks_per_cu(t.C, t.T, mode) !=
-                   stream_single_blocks_per_cu(t.C, t.T, mode, false)) {
+                   stream_single_blocks_per_cu(t.C, t.T, mode, false,
+                                               likely_vector_only(s.w, t.C, t.T))) {
         // the trajectory variant holds fewer waves: fill its rounds instead
         t.R = default_rows(s.n, s.h, s.w, t.C, t.T, dev, mode, true);
     }

@@ -107,7 +107,13 @@ hipError_t launch_stream_batched(int C, int T, int mode, const ImageDesc* dtable
                                  const int32_t* owner, int64_t total_items, const LaunchArgs& a,
                                  hipStream_t st);
 int stream_blocks_per_cu(int C, int T, int mode);
-int stream_single_blocks_per_cu(int C, int T, int mode, bool argmin);
+// Occupancy of a single-launch variant; vonly: the vector-only build that a
+// launch whose strips all qualify uses (vector_only).
+int stream_single_blocks_per_cu(int C, int T, int mode, bool argmin, bool vonly = false);
+// Whether every strip of a launch over image d with C columns per lane moves
+// its rows with vector accesses: aligned rows (d.vec), at least two strips,
+// the last strip starting at a multiple of C.
+bool vector_only(const ImageDesc& d, int C);
 int stream_traj_blocks_per_cu(int C, int T, int mode);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);

@@ -319,7 +319,11 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
 }
 
 // Resolves work item `item` of image d into an Item and runs it.
-template <int C, int T, int MODE, bool AM, bool TRAJ = false>
+// VONLY: every strip of the launch moves its rows with vector accesses (the
+// host checks it: aligned rows, at least two strips, the last one starting
+// at a multiple of C), so the clamped scalar paths are not compiled in --
+// they would otherwise set the register allocation of the whole kernel.
+template <int C, int T, int MODE, bool AM, bool TRAJ = false, bool VONLY = false>
 __device__ __forceinline__ void process(const ImageDesc& d, int64_t local, const LaunchArgs& a,
                                         float* ring) {
     const int64_t per_plane = (int64_t)d.nseg * d.nstrip;
@@ -363,7 +367,10 @@ __device__ __forceinline__ void process(const ImageDesc& d, int64_t local, const
     const float lam = a.lam ? a.lam[d.lam_index + ch * d.lam_stride] : 0.0f;
     if constexpr (MODE == kL1) it.k = make_coef_l1(lam, a.dt, a.alpha);
     else it.k = make_coef(lam, a.dt, MODE == kData);
-    if (first || lastS) {
+    if constexpr (VONLY) {
+        if (first || lastS) run_item<C, T, MODE, AM, kBorder, true, TRAJ>(it, ring);
+        else run_item<C, T, MODE, AM, kInterior, true, TRAJ>(it, ring);
+    } else if (first || lastS) {
         if (!(first && lastS) && it.vec && it.x0 % C == 0)
             run_item<C, T, MODE, AM, kBorder, true, TRAJ>(it, ring);
         else
@@ -380,7 +387,7 @@ constexpr int ring_floats() {
     return (MODE == kData || MODE == kL1) ? kWavesPerBlock * (T + 1) * 64 * C : 1;
 }
 
-template <int C, int T, int MODE, bool AM>
+template <int C, int T, int MODE, bool AM, bool VONLY = false>
 __global__ __launch_bounds__(kBlock) void k_stream_single(ImageDesc d, LaunchArgs a) {
     __shared__ float ring[ring_floats<C, T, MODE>()];
     // wave index, made visibly wave-uniform so that all work-item bookkeeping
@@ -389,8 +396,8 @@ __global__ __launch_bounds__(kBlock) void k_stream_single(ImageDesc d, LaunchArg
     const int64_t total = (int64_t)d.channels * d.nseg * d.nstrip;
     const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
     if (item >= total) return;
-    process<C, T, MODE, AM>(d, item, a,
-                            ring + ((MODE == kData || MODE == kL1) ? wv * (T + 1) * 64 * C : 0));
+    process<C, T, MODE, AM, false, VONLY>(
+        d, item, a, ring + ((MODE == kData || MODE == kL1) ? wv * (T + 1) * 64 * C : 0));
 }
 
 // Trajectory variant of k_stream_single: also stores the states after the
@@ -505,26 +512,27 @@ static int cindex(int C) { return C == 1 ? 0 : (C == 2 ? 1 : (C == 4 ? 2 : -1));
 
 #define WMC_T_LIST(X, C, M) X(C, 1, M) X(C, 2, M) X(C, 3, M) X(C, 4, M) X(C, 6, M) X(C, 8, M)
 
-static SingleFn single_table(int C, int T, int mode, bool am) {
+template <bool V>
+static SingleFn single_table_v(int C, int T, int mode, bool am) {
     const int ci = cindex(C), ti = tindex(T);
     if (ci < 0 || ti < 0) return nullptr;
     if (mode == kModeCompute) {
         if (T != 1) return nullptr;
         static const SingleFn tab[3][2] = {
-            {k_stream_single<1, 1, kCompute, false>, k_stream_single<1, 1, kCompute, true>},
-            {k_stream_single<2, 1, kCompute, false>, k_stream_single<2, 1, kCompute, true>},
-            {k_stream_single<4, 1, kCompute, false>, k_stream_single<4, 1, kCompute, true>}};
+            {k_stream_single<1, 1, kCompute, false, V>, k_stream_single<1, 1, kCompute, true, V>},
+            {k_stream_single<2, 1, kCompute, false, V>, k_stream_single<2, 1, kCompute, true, V>},
+            {k_stream_single<4, 1, kCompute, false, V>, k_stream_single<4, 1, kCompute, true, V>}};
         return tab[ci][am ? 1 : 0];
     }
     if (am) {
         if (T != 1) return nullptr;
         static const SingleFn tab[3][2] = {
-            {k_stream_single<1, 1, kData, true>, k_stream_single<1, 1, kFlow, true>},
-            {k_stream_single<2, 1, kData, true>, k_stream_single<2, 1, kFlow, true>},
-            {k_stream_single<4, 1, kData, true>, k_stream_single<4, 1, kFlow, true>}};
+            {k_stream_single<1, 1, kData, true, V>, k_stream_single<1, 1, kFlow, true, V>},
+            {k_stream_single<2, 1, kData, true, V>, k_stream_single<2, 1, kFlow, true, V>},
+            {k_stream_single<4, 1, kData, true, V>, k_stream_single<4, 1, kFlow, true, V>}};
         return tab[ci][mode == kModeData ? 0 : 1];
     }
-#define WMC_S(C, T, M) k_stream_single<C, T, M, false>,
+#define WMC_S(C, T, M) k_stream_single<C, T, M, false, V>,
     static const SingleFn data_tab[3][6] = {{WMC_T_LIST(WMC_S, 1, kData)},
                                             {WMC_T_LIST(WMC_S, 2, kData)},
                                             {WMC_T_LIST(WMC_S, 4, kData)}};
@@ -539,6 +547,10 @@ static SingleFn single_table(int C, int T, int mode, bool am) {
     }
 #undef WMC_S
     return mode == kModeData ? data_tab[ci][ti] : flow_tab[ci][ti];
+}
+
+static SingleFn single_table(int C, int T, int mode, bool am, bool vonly = false) {
+    return vonly ? single_table_v<true>(C, T, mode, am) : single_table_v<false>(C, T, mode, am);
 }
 
 static BatchedFn batched_table(int C, int T, int mode) {
@@ -600,9 +612,13 @@ bool stream_variant_exists(int C, int T, int mode, bool argmin) {
     return single_table(C, T, mode, argmin) != nullptr;
 }
 
+bool vector_only(const ImageDesc& d, int C) {
+    return d.vec != 0 && d.nstrip >= 2 && (d.W - 64 * C) % C == 0;
+}
+
 hipError_t launch_stream_single(int C, int T, int mode, bool argmin, const ImageDesc& d,
                                 const LaunchArgs& a, hipStream_t st) {
-    SingleFn fn = single_table(C, T, mode, argmin);
+    SingleFn fn = single_table(C, T, mode, argmin, vector_only(d, C));
     if (!fn) return hipErrorInvalidValue;
     const int64_t total = (int64_t)d.channels * d.nseg * d.nstrip;
     const int64_t blocks = (total + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -612,8 +628,8 @@ hipError_t launch_stream_single(int C, int T, int mode, bool argmin, const Image
     return hipGetLastError();
 }
 
-int stream_single_blocks_per_cu(int C, int T, int mode, bool argmin) {
-    SingleFn fn = single_table(C, T, mode, argmin);
+int stream_single_blocks_per_cu(int C, int T, int mode, bool argmin, bool vonly) {
+    SingleFn fn = single_table(C, T, mode, argmin, vonly);
     if (!fn) return 0;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn), kBlock,
