@@ -344,6 +344,10 @@ def main():
                    f"{tuning['tsteps']} sweeps/launch)"},
         "roofline": roofline,
         "roofline_other_bound": other,
+        "traffic_note": "roofline.traffic = FETCH_SIZE + WRITE_SIZE per launch (rocprofv3, scaled "
+                        "by a 1 GiB copy): traffic leaving the L2, Infinity Cache hits included "
+                        "(the 192 MiB working set fits the 256 MB cache); extras.step_T1_8192 "
+                        "is the update beyond the cache, against the probe of the same run",
         "step_equivalent_hbm_frac": round(BYTES_PER_PX_PASS * value / HBM_PEAK_GBS, 4),
         "paper_context": "33.2 Gpixel/s for the operator alone on an NVIDIA TITAN X (Pascal), "
                          "workload unstated (context only)",
