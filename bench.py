@@ -184,7 +184,7 @@ def train_step_fn(torch, wmc, wmc_synth, dev, ckpt_every=5):
 
     def step():
         u = wmc.WMCSolve.apply(xg, lam16, 20, 0.0, ckpt_every)
-        loss = torch.mean((u - y) ** 2)
+        loss = torch.nn.functional.mse_loss(u, y)   # mean((u - y)^2), fused by torch
         loss.backward()
     return step, x
 
@@ -427,7 +427,7 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side, only=None):
 
         def step5():
             u = wmc.WMCSolve.apply(x5, torch.exp(theta)[k5], 30, 0.0, 6)
-            torch.mean((u - y5) ** 2).backward()
+            torch.nn.functional.mse_loss(u, y5).backward()
         step5()
         ms = timed(step5, 20, stream, torch) / 20
         ms_d, hid = timed_device(step5, 20, stream, torch, host_ms_per_call=3.0)

@@ -140,6 +140,7 @@ struct AdjItem {
     float delta, lam, keep, coef;
     bool dlam_default;  // delta = 1/(1+lam): dU'/dlam has the delta'(lam) term
     bool gf_first;      // g_f is not read (taken as zero) but written
+    bool gf_fold;       // the last step of a solve from U^0 = f: dL/df also gets g_prev
 };
 
 template <int P>
@@ -177,6 +178,7 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
     FRow<C> fw[3];                                    // field rows n-3..n-1
     float gr[3][C], fr[3][C], gfr[3][C];              // g, f and dL/df rows n-2..n
     float topfold[C], pend[C], pendg[C];  // row -1 fold; row H-1 held until row H is done
+    float pendgf[C];                      // with gf_fold: dL/df of row H-1, held likewise
 #pragma unroll
     for (int j = 0; j < 3; ++j) zero_frow(fw[j]);
 #pragma unroll
@@ -184,6 +186,7 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
         topfold[e] = 0.0f;
         pend[e] = 0.0f;
         pendg[e] = 0.0f;
+        pendgf[e] = 0.0f;
     }
     float contrib = 0.0f;
 
@@ -234,11 +237,21 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
         }
     };
 
-    auto store = [&](int r, const float (&acc)[C], const float (&gv)[C]) {
+    // g_prev of row r; with gf_fold also dL/df(r) = gf (this step's value of
+    // row r, held back by stage A) + g_prev(r), the path through U^0 = f
+    auto store = [&](int r, const float (&acc)[C], const float (&gv)[C], const float (&gf)[C]) {
         float* dp = it.g_prev + (int64_t)r * (int64_t)it.ld;
         float v[C];
 #pragma unroll
         for (int e = 0; e < C; ++e) v[e] = __builtin_fmaf(it.coef, acc[e], it.keep * gv[e]);
+        if constexpr (DATA) {
+            if (it.gf_fold) {
+                float* qp = it.g_f + (int64_t)r * (int64_t)it.ld;
+#pragma unroll
+                for (int e = 0; e < C; ++e)
+                    if (own[e]) st_at<float>(qp, (uint32_t)(xb + e), gf[e] + v[e]);
+            }
+        }
         if constexpr (VEC) {
             if (all_own) {
                 if constexpr (C == 4) st_at<float4>(dp, (uint32_t)xb, make_float4(v[0], v[1], v[2], v[3]));
@@ -307,9 +320,10 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
                                 dudl -= it.delta * it.delta * ((fr[PM][e] - uw[PM].c[e]) + it.lam * hd);
                             const float c1 = __builtin_fmaf(gv, dudl, contrib);
                             contrib = own[e] ? c1 : contrib;
-                            if (gfp && own[e])
-                                st_at<float>(gfp, (uint32_t)(xb + e),
-                                             __builtin_fmaf(it.delta, gv, it.gf_first ? 0.0f : gfr[PM][e]));
+                            const float gfn =
+                                __builtin_fmaf(it.delta, gv, it.gf_first ? 0.0f : gfr[PM][e]);
+                            if (it.gf_fold) gfr[PM][e] = gfn;  // stored by stage B with g_prev
+                            else if (gfp && own[e]) st_at<float>(gfp, (uint32_t)(xb + e), gfn);
                         }
                     }
                 }
@@ -352,7 +366,7 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
             } else if (bot) {
 #pragma unroll
                 for (int e = 0; e < C; ++e) acc[e] += pend[e];
-                store(H - 1, acc, pendg);
+                store(H - 1, acc, pendg, pendgf);
             } else {
                 if (!ST && r == 0) {
 #pragma unroll
@@ -363,9 +377,10 @@ __device__ __forceinline__ float run_adj(const AdjItem it) {
                     for (int e = 0; e < C; ++e) {
                         pend[e] = acc[e];
                         pendg[e] = gr[PT][e];
+                        pendgf[e] = gfr[PT][e];
                     }
                 } else {
-                    store(r, acc, gr[PT]);
+                    store(r, acc, gr[PT], gfr[PT]);
                 }
             }
         }
@@ -456,6 +471,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_stream(AdjArgs A) {
     it.coef = DATA ? cf.delta * cf.lam12 : cf.delta12;
     it.dlam_default = !(A.dt > 0.0f);
     it.gf_first = A.gf_first != 0;
+    it.gf_fold = DATA && it.g_f && A.gf_fold != 0;
     const bool edge = it.x0 < 0 || it.x0 + 64 * C > W;
     float c;
     if (edge) c = run_adj<C, DATA, true, false>(it);

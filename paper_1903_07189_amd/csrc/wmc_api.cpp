@@ -1573,6 +1573,8 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
             a.g = gcur;
             a.g_prev = dst;
             a.slot = G - 1 - used;
+            // the last step adds dL/dU^0 into dL/df itself when U^0 = f
+            a.gf_fold = (left == 1 && data && g_f && !u0) ? 1 : 0;
             e = launch_adjoint_step(a, st);
             if (e != hipSuccess) return hip_fail(e, "adjoint launch");
             a.gf_first = 0;
@@ -1595,7 +1597,7 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
         e = launch_copy_planes(g_out, g_u0, s.n, s.h, s.w, s.ld, s.ps, st);
         if (e != hipSuccess) return hip_fail(e, "copy");
     }
-    if (data && g_f && !u0) {
+    if (data && g_f && !u0 && iters == 0) {
         e = launch_add_planes(gcur, g_f, s.n, s.h, s.w, s.ld, s.ps, st);
         if (e != hipSuccess) return hip_fail(e, "accumulate");
     }

@@ -140,6 +140,7 @@ struct AdjArgs {
     int32_t vec;        // 1: all row starts 4C-byte aligned
     int32_t slot;       // step slot of `part`
     int32_t gf_first;   // 1: the first adjoint step, g_f holds nothing yet (taken as zero)
+    int32_t gf_fold;    // 1: the last step of a solve from U^0 = f: g_f += g_prev as well
 };
 int adj_strip_count(int W, int C);
 int adj_rows(int64_t n, int64_t h, int64_t w, int C);
