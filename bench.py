@@ -428,7 +428,8 @@ def extras(torch, wmc, wmc_synth, f, lam, stream, side, only=None):
         def step5():
             u = wmc.WMCSolve.apply(x5, torch.exp(theta)[k5], 30, 0.0, 6)
             torch.nn.functional.mse_loss(u, y5).backward()
-        step5()
+        for _ in range(3):
+            step5()
         ms = timed(step5, 20, stream, torch) / 20
         ms_d, hid = timed_device(step5, 20, stream, torch, host_ms_per_call=3.0)
         ex["c5_train_step"] = {"ms": round(ms, 3), "ms_device": round(ms_d / 20, 3),
@@ -550,7 +551,8 @@ def _train(torch, wmc, wmc_synth, f, stream):
     lam16 = torch.ones(16, device=f.device)
     for name, c in (("c4_train_step", 5), ("c4_train_step_every_state", 1)):
         train_step, x = train_step_fn(torch, wmc, wmc_synth, f.device, c)
-        train_step()
+        for _ in range(3):   # warm-up: first-call set-up (tuning, plan caches) outside the timing
+            train_step()
         ms_t = timed(train_step, 20, stream, torch) / 20
         # the same steps with the host's enqueueing hidden behind a spin
         # kernel: the device time of a step

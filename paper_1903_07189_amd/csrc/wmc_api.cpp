@@ -175,9 +175,9 @@ bool likely_vector_only(int64_t w, int C, int T) {
 }
 
 int64_t resident_waves(int dev, int C, int T, int mode, bool traj = false, int64_t w = 0) {
-    int per_cu = traj ? stream_traj_blocks_per_cu(C, T, mode)
-                      : stream_single_blocks_per_cu(C, T, mode, false,
-                                                    w > 0 && likely_vector_only(w, C, T));
+    const bool vo = w > 0 && likely_vector_only(w, C, T);
+    int per_cu = traj ? stream_traj_blocks_per_cu(C, T, mode, vo)
+                      : stream_single_blocks_per_cu(C, T, mode, false, vo);
     if (per_cu <= 0) per_cu = 1;
     return (int64_t)num_cu(dev) * per_cu * 4;  // 4 waves per 256-thread block
 }
@@ -1114,7 +1114,7 @@ int wmc::solve_impl(const float* f, const float* u0, float* u_out, const float* 
         t.T = kTrajMaxT;
         t.R = default_rows(s.n, s.h, s.w, t.C, t.T, dev, mode, true);
     } else if (nck && t.T >= 2 && t.T <= kTrajMaxT && !tuning_complete(tune) &&
-               stream_traj_blocks_per_cu(t.C, t.T, mode) !=
+               stream_traj_blocks_per_cu(t.C, t.T, mode, likely_vector_only(s.w, t.C, t.T)) !=
                    stream_single_blocks_per_cu(t.C, t.T, mode, false,
                                                likely_vector_only(s.w, t.C, t.T))) {
         // the trajectory variant holds fewer waves: fill its rounds instead

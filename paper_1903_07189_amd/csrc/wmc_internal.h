@@ -114,7 +114,7 @@ int stream_single_blocks_per_cu(int C, int T, int mode, bool argmin, bool vonly 
 // its rows with vector accesses: aligned rows (d.vec), at least two strips,
 // the last strip starting at a multiple of C.
 bool vector_only(const ImageDesc& d, int C);
-int stream_traj_blocks_per_cu(int C, int T, int mode);
+int stream_traj_blocks_per_cu(int C, int T, int mode, bool vonly = false);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 hipError_t launch_copy_planes(const float* src, float* dst, int64_t n, int64_t h, int64_t w,

@@ -402,14 +402,15 @@ __global__ __launch_bounds__(kBlock) void k_stream_single(ImageDesc d, LaunchArg
 
 // Trajectory variant of k_stream_single: also stores the states after the
 // intermediate sweeps (checkpoints that fall inside a fused launch).
-template <int C, int T, int MODE>
+template <int C, int T, int MODE, bool VONLY = false>
 __global__ __launch_bounds__(kBlock, (C == 2 ? 3 : 1)) void k_stream_traj(ImageDesc d, LaunchArgs a) {
     __shared__ float ring[ring_floats<C, T, MODE>()];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t total = (int64_t)d.channels * d.nseg * d.nstrip;
     const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + wv;
     if (item >= total) return;
-    process<C, T, MODE, false, true>(d, item, a, ring + (MODE == kData ? wv * (T + 1) * 64 * C : 0));
+    process<C, T, MODE, false, true, VONLY>(d, item, a,
+                                            ring + (MODE == kData ? wv * (T + 1) * 64 * C : 0));
 }
 
 // Batched variant: one flat launch over the work items of many images (each
@@ -567,20 +568,29 @@ static BatchedFn batched_table(int C, int T, int mode) {
     return mode == kModeData ? data_tab[ci][ti] : flow_tab[ci][ti];
 }
 
+bool vector_only(const ImageDesc& d, int C) {
+    return d.vec != 0 && d.nstrip >= 2 && (d.W - 64 * C) % C == 0;
+}
+
+template <bool V>
+static SingleFn traj_table_v(int C, int T, int mode) {
+    const int ci = cindex(C);
+    if (ci < 0 || T < 2 || T > kTrajMaxT || (mode != kModeData && mode != kModeFlow)) return nullptr;
+#define WMC_TR(C, M) {k_stream_traj<C, 2, M, V>, k_stream_traj<C, 3, M, V>, k_stream_traj<C, 4, M, V>}
+    static const SingleFn data_tab[3][3] = {WMC_TR(1, kData), WMC_TR(2, kData), WMC_TR(4, kData)};
+    static const SingleFn flow_tab[3][3] = {WMC_TR(1, kFlow), WMC_TR(2, kFlow), WMC_TR(4, kFlow)};
+#undef WMC_TR
+    return mode == kModeData ? data_tab[ci][T - 2] : flow_tab[ci][T - 2];
+}
+
+static SingleFn traj_table(int C, int T, int mode, bool vonly) {
+    return vonly ? traj_table_v<true>(C, T, mode) : traj_table_v<false>(C, T, mode);
+}
+
 hipError_t launch_stream_traj(int C, int T, int mode, const ImageDesc& d, const LaunchArgs& a,
                               hipStream_t st) {
-    const int ci = cindex(C);
-    if (ci < 0 || T < 2 || T > kTrajMaxT || (mode != kModeData && mode != kModeFlow))
-        return hipErrorInvalidValue;
-    static const SingleFn data_tab[3][3] = {
-        {k_stream_traj<1, 2, kData>, k_stream_traj<1, 3, kData>, k_stream_traj<1, 4, kData>},
-        {k_stream_traj<2, 2, kData>, k_stream_traj<2, 3, kData>, k_stream_traj<2, 4, kData>},
-        {k_stream_traj<4, 2, kData>, k_stream_traj<4, 3, kData>, k_stream_traj<4, 4, kData>}};
-    static const SingleFn flow_tab[3][3] = {
-        {k_stream_traj<1, 2, kFlow>, k_stream_traj<1, 3, kFlow>, k_stream_traj<1, 4, kFlow>},
-        {k_stream_traj<2, 2, kFlow>, k_stream_traj<2, 3, kFlow>, k_stream_traj<2, 4, kFlow>},
-        {k_stream_traj<4, 2, kFlow>, k_stream_traj<4, 3, kFlow>, k_stream_traj<4, 4, kFlow>}};
-    SingleFn fn = mode == kModeData ? data_tab[ci][T - 2] : flow_tab[ci][T - 2];
+    SingleFn fn = traj_table(C, T, mode, vector_only(d, C));
+    if (!fn) return hipErrorInvalidValue;
     const int64_t total = (int64_t)d.channels * d.nseg * d.nstrip;
     const int64_t blocks = (total + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks <= 0) return hipSuccess;
@@ -589,18 +599,9 @@ hipError_t launch_stream_traj(int C, int T, int mode, const ImageDesc& d, const 
     return hipGetLastError();
 }
 
-int stream_traj_blocks_per_cu(int C, int T, int mode) {
-    const int ci = cindex(C);
-    if (ci < 0 || T < 2 || T > kTrajMaxT || (mode != kModeData && mode != kModeFlow)) return 0;
-    static const SingleFn data_tab[3][3] = {
-        {k_stream_traj<1, 2, kData>, k_stream_traj<1, 3, kData>, k_stream_traj<1, 4, kData>},
-        {k_stream_traj<2, 2, kData>, k_stream_traj<2, 3, kData>, k_stream_traj<2, 4, kData>},
-        {k_stream_traj<4, 2, kData>, k_stream_traj<4, 3, kData>, k_stream_traj<4, 4, kData>}};
-    static const SingleFn flow_tab[3][3] = {
-        {k_stream_traj<1, 2, kFlow>, k_stream_traj<1, 3, kFlow>, k_stream_traj<1, 4, kFlow>},
-        {k_stream_traj<2, 2, kFlow>, k_stream_traj<2, 3, kFlow>, k_stream_traj<2, 4, kFlow>},
-        {k_stream_traj<4, 2, kFlow>, k_stream_traj<4, 3, kFlow>, k_stream_traj<4, 4, kFlow>}};
-    SingleFn fn = mode == kModeData ? data_tab[ci][T - 2] : flow_tab[ci][T - 2];
+int stream_traj_blocks_per_cu(int C, int T, int mode, bool vonly) {
+    SingleFn fn = traj_table(C, T, mode, vonly);
+    if (!fn) return 0;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(fn), kBlock,
                                                      0) != hipSuccess)
@@ -610,10 +611,6 @@ int stream_traj_blocks_per_cu(int C, int T, int mode) {
 
 bool stream_variant_exists(int C, int T, int mode, bool argmin) {
     return single_table(C, T, mode, argmin) != nullptr;
-}
-
-bool vector_only(const ImageDesc& d, int C) {
-    return d.vec != 0 && d.nstrip >= 2 && (d.W - 64 * C) % C == 0;
 }
 
 hipError_t launch_stream_single(int C, int T, int mode, bool argmin, const ImageDesc& d,
