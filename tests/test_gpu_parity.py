@@ -165,6 +165,36 @@ def test_strided_layout(wmc):
         tie_aware_step(got[p], to_np(view[p]), to_np(fview[p]), 1.0, 0.5)
 
 
+def test_vector_only_build_matches_general(wmc):
+    """The vector-only kernel builds (taken when every strip moves its rows
+    with vector accesses) give bitwise the results of the general builds
+    (taken here through a padded layout whose odd row stride leaves rows
+    unaligned), for the operator, a step, fused solves and trajectories."""
+    rng = np.random.default_rng(40)
+    f = to_gpu(rng.uniform(0, 1, size=(2, 70, 300)))       # 300 columns: every C qualifies
+    pad_f = torch.zeros((2, 70, 301), device="cuda:0")
+    pad_f[:, :, :300] = f
+    fv = pad_f[:, :, :300]                                   # ld = 301: unaligned rows
+    assert fv.stride(1) == 301
+    lam = torch.tensor([0.8, 2.0], device="cuda:0")
+    assert torch.equal(wmc.compute(f), wmc.compute(fv))
+    assert torch.equal(wmc.step(f, f, lam), wmc.step(fv, fv, lam))
+    for c, t, r in [(2, 1, 8), (4, 1, 3), (2, 3, 16), (4, 4, 35), (2, 2, 5), (4, 2, 64)]:
+        tn = {"cols": c, "tsteps": t, "seg_rows": r}
+        a = wmc.solve(f, lam, 9, tuning=tn)
+        b = wmc.solve(fv, lam, 9, tuning=tn)
+        assert torch.equal(a, b), (c, t, r)
+    # checkpoints stored from inside fused launches (vector-only trajectory
+    # builds here) are the states of single steps (general builds)
+    a, ck = wmc.solve(f, lam, 9, ckpt_every=2, tuning={"cols": 2, "tsteps": 4, "seg_rows": 16})
+    u = fv
+    for t in range(9):
+        if t % 2 == 0:
+            assert torch.equal(ck[t // 2], u.contiguous()), t
+        u = wmc.step(u, fv, lam)
+    assert torch.equal(a, u.contiguous())
+
+
 TUNINGS = [(c, t, r) for c in (1, 2, 4) for t in (1, 2, 3, 4, 6, 8) for r in (1, 5, 16, 64)]
 
 
