@@ -183,6 +183,10 @@ def train_step_fn(torch, wmc, wmc_synth, dev, ckpt_every=5):
     xg = x.clone().requires_grad_(True)
 
     def step():
+        # gradients cleared as an optimiser's zero_grad(set_to_none=True) does,
+        # so autograd stores the new ones instead of adding them to the last
+        xg.grad = None
+        lam16.grad = None
         u = wmc.WMCSolve.apply(xg, lam16, 20, 0.0, ckpt_every)
         loss = torch.nn.functional.mse_loss(u, y)   # mean((u - y)^2), fused by torch
         loss.backward()

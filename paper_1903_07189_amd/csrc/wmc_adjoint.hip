@@ -485,7 +485,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_adj_stream(AdjArgs A) {
 // work items (per thread in item order, then a fixed tree over the 256
 // threads) into sums[p * steps + j].  k_lam_accumulate: per plane,
 // g_lam[p] += the slot sums from the last slot to the first, one addition
-// at a time.  Every slot is reduced at once, so the launch fills the device
+// at a time, starting from zero instead of g_lam[p] for the first group of
+// a backward pass (0 + x = x exactly, so no separate clearing launch).  Every slot is reduced at once, so the launch fills the device
 // instead of running one block per plane.
 __global__ __launch_bounds__(256) void k_lam_slot_sums(const float* __restrict__ part, int64_t total,
                                                        int64_t per_plane, int steps,
@@ -505,10 +506,11 @@ __global__ __launch_bounds__(256) void k_lam_slot_sums(const float* __restrict__
 }
 
 __global__ __launch_bounds__(256) void k_lam_accumulate(const float* __restrict__ sums, int steps,
-                                                        int64_t n, float* __restrict__ g_lam) {
+                                                        int64_t n, int first,
+                                                        float* __restrict__ g_lam) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
-    float acc = g_lam[p];
+    float acc = first ? 0.0f : g_lam[p];
     for (int j = steps - 1; j >= 0; --j) acc += sums[p * steps + j];
     g_lam[p] = acc;
 }
@@ -548,14 +550,14 @@ hipError_t launch_adjoint_step(const AdjArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_lambda_reduce(const float* part, int steps, int64_t total, int64_t per_plane,
-                                int64_t n, float* g_lam, float* sums, hipStream_t st) {
+                                int64_t n, bool first, float* g_lam, float* sums, hipStream_t st) {
     if (steps < 1 || n < 1 || n > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_lam_slot_sums, dim3((unsigned)steps, (unsigned)n), dim3(256), 0, st, part,
                        total, per_plane, steps, sums);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lam_accumulate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sums,
-                       steps, n, g_lam);
+                       steps, n, first ? 1 : 0, g_lam);
     return hipGetLastError();
 }
 

@@ -561,6 +561,7 @@ struct SLaunch {
     const float* src;
     float* dst;
     float* traj[3];  // checkpoints reached after sweeps 1..T-1 of this launch (or null)
+    float* traj_in;  // checkpoint 0 (the solve's U^0), stored by the first launch
 };
 
 // Launch sequence of a single plane-set solve.  Checkpoint states that fall
@@ -596,6 +597,9 @@ std::vector<SLaunch> solve_schedule(int iters, int T, int ckpt_every, const floa
         out[l].dst = dst;
         out[l].T = depth[l];
         for (int k = 0; k < 3; ++k) out[l].traj[k] = nullptr;
+        // a trajectory launch stores its input rows as it reads them, so the
+        // first one writes checkpoint 0 without a copy of its own
+        out[l].traj_in = (traj && l == 0 && depth[l] >= 2) ? ckpt : nullptr;
         if (traj) {
             const int t0 = end_t[l] - depth[l];
             for (int k = 1; k < depth[l]; ++k)
@@ -609,7 +613,7 @@ std::vector<SLaunch> solve_schedule(int iters, int T, int ckpt_every, const floa
 
 int enqueue_single(const wmc_shape& s, const float* src, const float* f, float* dst,
                    const float* lam, float dt, int C, int T, int R, hipStream_t st,
-                   float* const* traj = nullptr) {
+                   float* const* traj = nullptr, float* traj_in = nullptr) {
     const int mode = f ? kModeData : kModeFlow;
     const bool vec = vec_cols({src, f, dst}, s.ld, s.n > 1 ? s.ps : 0) >= C;
     ImageDesc d{};
@@ -628,7 +632,15 @@ int enqueue_single(const wmc_shape& s, const float* src, const float* f, float* 
     d.nseg = seg_count((int)s.h, R);
     d.vec = vec ? 1 : 0;
     LaunchArgs a{lam, dt, 0, 1, R};
-    bool any = false;
+    // the input state: stored by the launch itself when its vector-only
+    // build runs, else copied first
+    if (traj_in && !(T >= 2 && vector_only(d, C))) {
+        const hipError_t e = launch_copy_planes(src, traj_in, s.n, s.h, s.w, s.ld, s.ps, st);
+        if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+        traj_in = nullptr;
+    }
+    a.traj_in = traj_in;
+    bool any = a.traj_in != nullptr;
     for (int k = 0; traj && k < 3; ++k) {
         a.traj[k] = k < T - 1 ? traj[k] : nullptr;
         any = any || a.traj[k];
@@ -1124,12 +1136,13 @@ int wmc::solve_impl(const float* f, const float* u0, float* u_out, const float* 
         solve_schedule(iters, t.T, ckpt ? ckpt_every : 0, src0, u_out, static_cast<float*>(ws),
                        nck ? ckpt : nullptr, stride);
     auto enqueue = [&](hipStream_t ss, PlanEntry&) -> int {
-        if (nck) {
+        if (nck && !(sched.size() && sched[0].traj_in)) {
             const hipError_t e = launch_copy_planes(src0, ckpt, s.n, s.h, s.w, s.ld, s.ps, ss);
             if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
         }
         for (const SLaunch& L : sched) {
-            const int r = enqueue_single(s, L.src, f, L.dst, lam, dt, t.C, L.T, t.R, ss, L.traj);
+            const int r = enqueue_single(s, L.src, f, L.dst, lam, dt, t.C, L.T, t.R, ss, L.traj,
+                                         L.traj_in);
             if (r) return r;
         }
         return WMC_OK;
@@ -1531,7 +1544,10 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
     a.vec = vecA ? 1 : 0;
     const int64_t items = (int64_t)s.n * a.nstrip * a.nseg;
     hipError_t e;
-    if (g_lam) {
+    // dL/dlam: the first reduction of the partial sums starts from zero;
+    // only without one (flow mode, no step) is it cleared here
+    bool lam_first = true;
+    if (g_lam && !(a.part && iters >= 1)) {
         e = launch_fill_f32(g_lam, s.n, 0.0f, st);
         if (e != hipSuccess) return hip_fail(e, "fill");
     }
@@ -1582,15 +1598,17 @@ int wmc_backward(const float* f, const float* u0, const float* lam, int iters, f
             gcur = dst;
             --left;
             if (a.part && ++used == G) {
-                e = launch_lambda_reduce(part, G, items, items / s.n, s.n, g_lam, lam_sums, st);
+                e = launch_lambda_reduce(part, G, items, items / s.n, s.n, lam_first, g_lam,
+                                         lam_sums, st);
                 if (e != hipSuccess) return hip_fail(e, "lambda reduction");
+                lam_first = false;
                 used = 0;
             }
         }
     }
     if (a.part && used > 0) {
         e = launch_lambda_reduce(part + (int64_t)(G - used) * items, used, items, items / s.n, s.n,
-                                 g_lam, lam_sums, st);
+                                 lam_first, g_lam, lam_sums, st);
         if (e != hipSuccess) return hip_fail(e, "lambda reduction");
     }
     if (g_u0 && iters == 0) {

@@ -86,8 +86,10 @@ struct LaunchArgs {
     float alpha;       // l1 mode: dual bound
     // trajectory launches (k_stream_traj): the state after sweep k (1 <= k < T)
     // is also stored to traj[k-1] (a plane set with the layout of the image),
-    // or not at all where traj[k-1] is null
+    // or not at all where traj[k-1] is null; traj_in, if set, receives the
+    // launch's input state (sweep 0) the same way (vector-only builds only)
     float* traj[3];
+    float* traj_in;
 };
 
 constexpr int kTrajMaxT = 4;  // trajectory launches exist for T = 2, 3, 4
@@ -148,9 +150,10 @@ int64_t adj_items(int64_t n, int64_t h, int64_t w, int C);
 hipError_t launch_adjoint_step(const AdjArgs& a, hipStream_t st);
 // Adds the lambda partial sums of `steps` step slots (slot j at part +
 // j * total, plane p's items at p * per_plane) into g_lam, the last slot
-// first; `sums` holds n * steps floats of scratch.
+// first; with `first` the sum starts from zero and g_lam is not read.
+// `sums` holds n * steps floats of scratch.
 hipError_t launch_lambda_reduce(const float* part, int steps, int64_t total, int64_t per_plane,
-                                int64_t n, float* g_lam, float* sums, hipStream_t st);
+                                int64_t n, bool first, float* g_lam, float* sums, hipStream_t st);
 
 // Learnable half-window layer (wmc_layer.hip).
 int64_t layer_part_floats(int64_t n, int64_t h, int64_t w, int K);

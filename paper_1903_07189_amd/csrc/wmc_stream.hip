@@ -76,6 +76,7 @@ struct Item {
     bool vec;
     Coef k;
     float* traj[3];  // trajectory stores (plane offset applied), see LaunchArgs
+    float* traj_in;
 };
 
 
@@ -261,6 +262,9 @@ __device__ __forceinline__ void run_item(const Item it, float* __restrict__ ring
             }
             put_ring(n, pf[P]);
             if (n + 3 < hi0) load(pf[P], n + 3);
+            if constexpr (TRAJ && VEC) {
+                if (it.traj_in) store_traj(it.traj_in, n, m);  // the input state's owned rows
+            }
             if constexpr (KIND == kGeneric) make_row<C, true>(m, last, win[0][P]);
             else if constexpr (KIND == kBorder) make_row<C, false>(m, last, win[0][P]);
             else make_row_inner<C>(m, win[0][P]);
@@ -364,6 +368,9 @@ __device__ __forceinline__ void process(const ImageDesc& d, int64_t local, const
     it.vec = d.vec != 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) it.traj[k] = (TRAJ && a.traj[k]) ? a.traj[k] + poff : nullptr;
+    // the input state is stored by vector-only builds only (the host copies
+    // it otherwise): the clamped scalar path has no registers to spare
+    it.traj_in = (TRAJ && VONLY && a.traj_in) ? a.traj_in + poff : nullptr;
     const float lam = a.lam ? a.lam[d.lam_index + ch * d.lam_stride] : 0.0f;
     if constexpr (MODE == kL1) it.k = make_coef_l1(lam, a.dt, a.alpha);
     else it.k = make_coef(lam, a.dt, MODE == kData);

@@ -283,6 +283,46 @@ def test_checkpoints_inside_fused_launches(wmc, cols, tsteps, every, flow):
     assert torch.equal(out, u)
 
 
+@pytest.mark.parametrize("tsteps,every,ld", [(1, 3, 160), (2, 3, 160), (3, 3, 160), (4, 3, 160),
+                                              (4, 5, 160), (6, 6, 160), (4, 3, 161)])
+def test_checkpoint0_on_padded_rows(wmc, tsteps, every, ld):
+    """Checkpoint 0 (= f) is stored by the first trajectory launch as it
+    reads its input rows (T = 2..4 with rows moved by vector accesses), or by
+    a plane copy (T = 1, a deeper T whose launches end at the checkpoints, or
+    an odd row stride): either way it is f bitwise, on a padded row layout
+    whose padding stays untouched, and the solve's result is that of the same
+    solve on the unpadded image."""
+    import ctypes
+    from paper_1903_07189_amd import wmc as M
+    L = M.lib()
+    n, h, w, K = 2, 41, 150, 13
+    ps = h * ld + 32
+    rng = np.random.default_rng(40 + tsteps + every)
+    base = rng.uniform(0, 1, size=n * ps).astype(np.float32)
+    f = to_gpu(base)
+    s = M.Shape(n, h, w, ld, ps)
+    setst = L.wmc_set_stride(s)
+    nck = L.wmc_num_checkpoints(K, every)
+    ck = torch.full((nck * setst,), float("nan"), device=dev())
+    out = torch.full((n * ps,), float("nan"), device=dev())
+    ws = torch.empty(L.wmc_solve_workspace(s) // 4 + 64, device=dev())
+    lt = torch.full((n,), 0.7, device=dev())
+    tn = M.Tuning(2, tsteps, 9, 1)
+    M.check(L.wmc_solve(M._ptr(f), None, M._ptr(out), M._ptr(lt), K, 0.0, M._ptr(ck), every,
+                        ctypes.byref(tn), M._ptr(ws), ws.numel() * 4, s, M._stream()))
+    c0 = ck[:setst].cpu().numpy()
+    o = out.cpu().numpy()
+    img = np.stack([base[v * ps: v * ps + h * ld].reshape(h, ld)[:, :w] for v in range(n)])
+    ref = wmc.solve(to_gpu(img), 0.7, K, tuning={"cols": 2, "tsteps": tsteps, "seg_rows": 9}).cpu().numpy()
+    for v in range(n):
+        rows = c0[v * ps: v * ps + h * ld].reshape(h, ld)
+        assert np.array_equal(rows[:, :w], img[v])
+        assert np.isnan(rows[:, w:]).all()
+        got = o[v * ps: v * ps + h * ld].reshape(h, ld)
+        assert np.array_equal(got[:, :w], ref[v])
+        assert np.isnan(got[:, w:]).all()
+
+
 def test_default_tuning_path(wmc, monkeypatch, tmp_path):
     """The autotuned default (no tuning given) is bitwise the same result."""
     monkeypatch.setenv("WMC_TUNE_CACHE", str(tmp_path / "tune.json"))
