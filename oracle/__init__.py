@@ -96,6 +96,9 @@ def _load():
         lib.wmco3_kernels.argtypes = [P]
         lib.wmco3_compute.argtypes = [P, I64, I64, I64, P, P]
         lib.wmco3_solve.argtypes = [P, P, I64, I64, I64, D, D, I, P]
+        lib.wmco3_step.argtypes = [P, P, I64, I64, I64, D, D, P, P, P]
+        lib.wmco3_step_adjoint.argtypes = [P, P, I64, I64, I64, D, D, I, P, P, P, P, P]
+        lib.wmco3_solve_adjoint.argtypes = [P, P, I64, I64, I64, D, D, I, I, P, P, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -432,3 +435,80 @@ def solve3(f=None, lam: float = 1.0, iters: int = 1, delta: float | None = None,
     out = np.empty_like(ref)
     _load().wmco3_solve(_p(f), _p(u0), D, H, W, float(lam), float(delta), int(iters), _p(out))
     return out
+
+
+def step3(U, f=None, lam: float = 1.0, delta: float | None = None, m_forced=None,
+          return_argmin: bool = False):
+    """One 3-D Jacobi step (O14 with O13's operator); m_forced replays a
+    selection (entries < 0: the first-minimum rule)."""
+    U = _d3(U)
+    D, H, W = U.shape
+    f = None if f is None else _d3(f)
+    if delta is None:
+        delta = default_delta(lam, f is None)
+    mf = None
+    if m_forced is not None:
+        mf = np.ascontiguousarray(m_forced, dtype=np.int8)
+        if mf.shape != U.shape:
+            raise ValueError("selection map shape mismatch")
+    out = np.empty_like(U)
+    m = np.empty(U.shape, dtype=np.int8)
+    _load().wmco3_step(_p(U), _p(f), D, H, W, float(lam), float(delta), _p(mf), _p(out), _p(m))
+    return (out, m) if return_argmin else out
+
+
+def step3_adjoint(U, gbar, f=None, lam: float = 1.0, delta: float | None = None,
+                  delta_from_lam: bool | None = None, m_forced=None):
+    """Adjoint of one 3-D step (O14).  Returns (gU, gf, glam); gf is None in
+    flow mode."""
+    U = _d3(U)
+    D, H, W = U.shape
+    f = None if f is None else _d3(f)
+    gbar = _d3(gbar)
+    if delta is None:
+        delta = default_delta(lam, f is None)
+        if delta_from_lam is None:
+            delta_from_lam = f is not None
+    delta_from_lam = bool(delta_from_lam)
+    mf = None
+    if m_forced is not None:
+        mf = np.ascontiguousarray(m_forced, dtype=np.int8)
+        if mf.shape != U.shape:
+            raise ValueError("selection map shape mismatch")
+    gU = np.empty_like(U)
+    gf = np.zeros_like(U) if f is not None else None
+    gl = ctypes.c_double(0.0)
+    _load().wmco3_step_adjoint(_p(U), _p(f), D, H, W, float(lam), float(delta), int(delta_from_lam),
+                               _p(mf), _p(gbar), _p(gU), _p(gf), ctypes.byref(gl))
+    return gU, gf, float(gl.value)
+
+
+def solve3_adjoint(gK, f=None, lam: float = 1.0, K: int = 1, delta: float | None = None,
+                   u0=None, delta_from_lam: bool | None = None, m_forced_all=None):
+    """Adjoint of a K-step 3-D solve (O14).  Returns dict with gu0, gf (data
+    term only), glam and UK."""
+    if f is None and u0 is None:
+        raise ValueError("flow mode needs u0")
+    f = None if f is None else _d3(f)
+    u0 = None if u0 is None else _d3(u0)
+    ref = f if f is not None else u0
+    D, H, W = ref.shape
+    gK = _d3(gK)
+    if delta is None:
+        delta = default_delta(lam, f is None)
+        if delta_from_lam is None:
+            delta_from_lam = f is not None
+    delta_from_lam = bool(delta_from_lam)
+    mf = None
+    if m_forced_all is not None:
+        mf = np.ascontiguousarray(m_forced_all, dtype=np.int8)
+        if mf.shape != (K, D, H, W):
+            raise ValueError("m_forced_all must be (K, D, H, W)")
+    gu0 = np.empty((D, H, W))
+    gf = np.empty((D, H, W)) if f is not None else None
+    UK = np.empty((D, H, W))
+    gl = ctypes.c_double(0.0)
+    _load().wmco3_solve_adjoint(_p(f), _p(u0), D, H, W, float(lam), float(delta),
+                                int(delta_from_lam), int(K), _p(mf), _p(gK), _p(gu0), _p(gf),
+                                ctypes.byref(gl), _p(UK))
+    return {"gu0": gu0, "gf": gf, "glam": float(gl.value), "UK": UK}

@@ -40,7 +40,8 @@
  *       respect to the input and the kernel weights;
  *   O13 the extension to 3-D volumes that the conclusion mentions (Sec. 6);
  *       the paper gives no kernels, so they are built the way Sec. 4.1 builds
- *       the 2-D ones (see O13 below).
+ *       the 2-D ones (see O13 below);
+ *   O14 the adjoint of the 3-D iteration, derived as O8 is for 2-D.
  *
  * Images are row-major H x W arrays of doubles, x = column, y = row
  * (downwards).  Functions never allocate more than O(H W) scratch.
@@ -520,31 +521,42 @@ static double ubar3(const double* U, int64_t D, int64_t H, int64_t W, int64_t z,
     return U[(clampi(z, 0, D - 1) * H + clampi(y, 0, H - 1)) * W + clampi(x, 0, W - 1)];
 }
 
+/* The 18 responses S_i (x56 domain) at voxel (z, y, x), difference form. */
+static void cands3_at(const double* U, int64_t D, int64_t H, int64_t W, int64_t z, int64_t y,
+                      int64_t x, const int* w, double S[18]) {
+    const double c = U[(z * H + y) * W + x];
+    for (int i = 0; i < 18; ++i) {
+        double acc = 0.0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int t = ((dz + 1) * 3 + (dy + 1)) * 3 + (dx + 1);
+                    if (t == 13 || !w[i * 27 + t]) continue;
+                    acc += w[i * 27 + t] * (ubar3(U, D, H, W, z + dz, y + dy, x + dx) - c);
+                }
+        S[i] = acc;
+    }
+}
+
+/* First index attaining the least |S_i| (strict '<'). */
+static int first_min18(const double S[18]) {
+    int m = 0;
+    for (int i = 1; i < 18; ++i)
+        if (fabs(S[i]) < fabs(S[m])) m = i;
+    return m;
+}
+
 void wmco3_compute(const double* U, int64_t D, int64_t H, int64_t W, double* Hd, int8_t* m_out) {
     int w[18 * 27];
+    double S[18];
     wmco3_kernels(w);
     for (int64_t z = 0; z < D; ++z)
         for (int64_t y = 0; y < H; ++y)
             for (int64_t x = 0; x < W; ++x) {
-                const double c = U[(z * H + y) * W + x];
-                double best = 0.0;
-                int bi = 0;
-                for (int i = 0; i < 18; ++i) {
-                    double S = 0.0;
-                    for (int dz = -1; dz <= 1; ++dz)
-                        for (int dy = -1; dy <= 1; ++dy)
-                            for (int dx = -1; dx <= 1; ++dx) {
-                                const int t = ((dz + 1) * 3 + (dy + 1)) * 3 + (dx + 1);
-                                if (t == 13 || !w[i * 27 + t]) continue;
-                                S += w[i * 27 + t] * (ubar3(U, D, H, W, z + dz, y + dy, x + dx) - c);
-                            }
-                    if (i == 0 || fabs(S) < fabs(best)) {
-                        best = S;
-                        bi = i;
-                    }
-                }
-                Hd[(z * H + y) * W + x] = best / 56.0;
-                if (m_out) m_out[(z * H + y) * W + x] = (int8_t)bi;
+                cands3_at(U, D, H, W, z, y, x, w, S);
+                const int m = first_min18(S);
+                Hd[(z * H + y) * W + x] = S[m] / 56.0;
+                if (m_out) m_out[(z * H + y) * W + x] = (int8_t)m;
             }
 }
 
@@ -563,4 +575,105 @@ void wmco3_solve(const double* f, const double* u0, int64_t D, int64_t H, int64_
     memcpy(Uout, a, sizeof(double) * n);
     free(a);
     free(h);
+}
+
+/* O14: one Jacobi step of the 3-D iteration (O13) with the selection
+ * replayable as in O5: m_forced (nullable) entries >= 0 replace the
+ * first-minimum rule; m_out (nullable) records the selection used.
+ * f == NULL is the flow U' = U + delta H. */
+void wmco3_step(const double* U, const double* f, int64_t D, int64_t H, int64_t W, double lam,
+                double delta, const int8_t* m_forced, double* Uout, int8_t* m_out) {
+    int w[18 * 27];
+    double S[18];
+    wmco3_kernels(w);
+    for (int64_t z = 0; z < D; ++z)
+        for (int64_t y = 0; y < H; ++y)
+            for (int64_t x = 0; x < W; ++x) {
+                const int64_t k = (z * H + y) * W + x;
+                cands3_at(U, D, H, W, z, y, x, w, S);
+                const int m = (m_forced && m_forced[k] >= 0) ? m_forced[k] : first_min18(S);
+                const double h = S[m] / 56.0;
+                Uout[k] = f ? U[k] + delta * ((f[k] - U[k]) + lam * h) : U[k] + delta * h;
+                if (m_out) m_out[k] = (int8_t)m;
+            }
+}
+
+/* O14: adjoint of one 3-D step, the counterpart of O8.  With m held fixed
+ * the step is affine in (U, f):
+ *   U'(x) = U(x) + delta[(f(x) - U(x)) + lam/56 sum_o w_m(x)[o] Ubar(x+o)]
+ * (w_i with its centre weight -56, Ubar the replicate-clamped voxel), so
+ * dL/dU(v) = keep gbar(v) + coef sum_{x, o : clamp(x+o) = v} w_m(x)[o] gbar(x)
+ * with keep = 1 - delta, coef = delta lam / 56 (data) or keep = 1,
+ * coef = delta / 56 (flow).  gf (nullable) += delta gbar; *glam (nullable)
+ * += sum gbar dU'/dlam with dU'/dlam = delta H, plus -delta^2((f - U) + lam H)
+ * when delta_from_lam (delta = 1/(1+lam)).  gU is overwritten. */
+void wmco3_step_adjoint(const double* U, const double* f, int64_t D, int64_t H, int64_t W,
+                        double lam, double delta, int delta_from_lam, const int8_t* m_forced,
+                        const double* gbar, double* gU, double* gf, double* glam) {
+    int w[18 * 27];
+    double S[18];
+    wmco3_kernels(w);
+    const int64_t n = D * H * W;
+    const double coef = f ? delta * lam / 56.0 : delta / 56.0;
+    const double keep = f ? 1.0 - delta : 1.0;
+    for (int64_t k = 0; k < n; ++k) gU[k] = keep * gbar[k];
+    double gl = 0.0;
+    for (int64_t z = 0; z < D; ++z)
+        for (int64_t y = 0; y < H; ++y)
+            for (int64_t x = 0; x < W; ++x) {
+                const int64_t k = (z * H + y) * W + x;
+                cands3_at(U, D, H, W, z, y, x, w, S);
+                const int m = (m_forced && m_forced[k] >= 0) ? m_forced[k] : first_min18(S);
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int t = ((dz + 1) * 3 + (dy + 1)) * 3 + (dx + 1);
+                            const int64_t v = (clampi(z + dz, 0, D - 1) * H + clampi(y + dy, 0, H - 1)) * W +
+                                              clampi(x + dx, 0, W - 1);
+                            gU[v] += coef * (double)w[m * 27 + t] * gbar[k];
+                        }
+                if (f) {
+                    const double h = S[m] / 56.0;
+                    if (gf) gf[k] += delta * gbar[k];
+                    double du = delta * h;
+                    if (delta_from_lam) du += -delta * delta * ((f[k] - U[k]) + lam * h);
+                    gl += gbar[k] * du;
+                }
+            }
+    if (glam) *glam += gl;
+}
+
+/* O14: adjoint of a K-step 3-D solve, all K states kept (small volumes).
+ * Outputs as O8: gu0 = dL/dU^0, gf = dL/df through the data term only (if
+ * the solve started from u0 = f the caller adds gu0), glam, UK = U^K; all
+ * nullable.  m_forced_all (nullable): K selection maps back to back. */
+void wmco3_solve_adjoint(const double* f, const double* u0, int64_t D, int64_t H, int64_t W,
+                         double lam, double delta, int delta_from_lam, int K,
+                         const int8_t* m_forced_all, const double* gK, double* gu0, double* gf,
+                         double* glam, double* UK) {
+    const int64_t n = D * H * W;
+    double* states = (double*)malloc(sizeof(double) * n * (size_t)(K + 1));
+    memcpy(states, u0 ? u0 : f, sizeof(double) * n);
+    for (int t = 0; t < K; ++t)
+        wmco3_step(states + (int64_t)t * n, f, D, H, W, lam, delta,
+                   m_forced_all ? m_forced_all + (int64_t)t * n : NULL,
+                   states + (int64_t)(t + 1) * n, NULL);
+    if (UK) memcpy(UK, states + (int64_t)K * n, sizeof(double) * n);
+    double* g = (double*)malloc(sizeof(double) * n);
+    double* g2 = (double*)malloc(sizeof(double) * n);
+    memcpy(g, gK, sizeof(double) * n);
+    if (gf) memset(gf, 0, sizeof(double) * n);
+    double gl = 0.0;
+    for (int t = K - 1; t >= 0; --t) {
+        wmco3_step_adjoint(states + (int64_t)t * n, f, D, H, W, lam, delta, delta_from_lam,
+                           m_forced_all ? m_forced_all + (int64_t)t * n : NULL, g, g2, gf, &gl);
+        double* tmp = g;
+        g = g2;
+        g2 = tmp;
+    }
+    if (gu0) memcpy(gu0, g, sizeof(double) * n);
+    if (glam) *glam = gl;
+    free(states);
+    free(g);
+    free(g2);
 }
