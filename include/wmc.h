@@ -296,10 +296,19 @@ int wmc_fd_flow(const float* u0, float* u_out, int iters, float dt, float eps, v
  * wmc3_step    -- one Jacobi update: u_out = u + dt[(f - u) + lam H(u)]
  *                 (f NULL: u + dt H(u)); dt <= 0 selects 1/(1+lam) (data)
  *                 or 1 (flow); lam: device array of n values (data mode).
+ *                 argmin_out: NULL, or a device byte map (layout s) that
+ *                 receives the 0-based index of the selected half window
+ *                 (2 j for the n_j.o <= 0 side of plane j, 2 j + 1 for the
+ *                 other); it must not overlap u, f or u_out.
  * wmc3_solve   -- iters such updates from u0 (NULL: f); ws: one volume set
- *                 (vs*n or the extent, floats) when iters >= 2.
- * Single sweeps per launch (no temporal blocking); the same errors as the
- * 2-D entry points.
+ *                 (wmc3_set_stride(s) floats) when iters >= 2.  ckpt (or
+ *                 NULL): wmc_num_checkpoints(iters, ckpt_every) volume sets,
+ *                 wmc3_set_stride(s) floats apart, receiving U^{j ckpt_every}
+ *                 (the restart points of wmc3_backward); ckpt must not
+ *                 overlap u_out, ws or the inputs.
+ * Single sweeps per launch (no temporal blocking: at about 120 lane
+ * operations per voxel the sweep is bound by the vector ALUs, not by the
+ * bytes a fused launch would save); the same errors as the 2-D entry points.
  * ------------------------------------------------------------------------- */
 typedef struct {
     int64_t n, d, h, w, ld, ss, vs;
@@ -307,10 +316,42 @@ typedef struct {
 
 int wmc3_compute(const float* u, float* hw, wmc_shape3 s, void* stream);
 int wmc3_step(const float* u, const float* f, float* u_out, const float* lam, float dt,
-              wmc_shape3 s, void* stream);
+              uint8_t* argmin_out, wmc_shape3 s, void* stream);
 size_t wmc3_solve_workspace(wmc_shape3 s);
+/* Elements between consecutive volume sets of a checkpoint buffer: n*vs, or
+ * the extent of the set if that is larger (0 for an invalid shape). */
+int64_t wmc3_set_stride(wmc_shape3 s);
 int wmc3_solve(const float* f, const float* u0, float* u_out, const float* lam, int iters,
-               float dt, void* ws, size_t ws_bytes, wmc_shape3 s, void* stream);
+               float dt, float* ckpt, int ckpt_every, void* ws, size_t ws_bytes, wmc_shape3 s,
+               void* stream);
+
+/* Bytes of workspace wmc3_backward needs. */
+size_t wmc3_backward_workspace(wmc_shape3 s, int iters, int ckpt_every);
+
+/* ---------------------------------------------------------------------------
+ * wmc3_backward -- reverse-mode derivative of L(U^iters) through wmc3_solve,
+ * the 3-D counterpart of wmc_backward (the paper leaves the gradient of the
+ * regulariser open, end of Sec. 3, and mentions volumes only in Sec. 6): the
+ * exact derivative of the update with the selected half window held at its
+ * forward value,
+ *   dL/dU^t(v) = k dL/dU^{t+1}(v)
+ *              + c sum_{x,o : clamp(x+o) = v} w_{m(x)}[o] dL/dU^{t+1}(x)
+ * (w the 18 half windows x56, centre -56; k = 1 - dt, c = dt lam / 56 with a
+ * data term, k = 1, c = dt / 56 for the flow), dL/df += dt dL/dU^{t+1}, and
+ * dL/dlam_v summed over the volume (with the dependence of the default
+ * dt = 1/(1+lam) on lam).  f, u0, lam, iters, dt, ckpt, ckpt_every: exactly
+ * as passed to the wmc3_solve that wrote ckpt (each segment is recomputed
+ * from its checkpoint).  g_out: dL/dU^iters.  Outputs (device, layout s,
+ * overwritten; each may be NULL): g_f (data term) dL/df including the path
+ * through U^0 = f when u0 == NULL; g_u0 dL/dU^0; g_lam n floats.
+ * Deterministic: fixed summation orders, no atomics; the gradients do not
+ * depend on ckpt_every.  Errors: WMC_EINVAL (shapes, NULL checkpoints with
+ * iters > 0, overlapping outputs), WMC_ENOMEM (ws smaller than
+ * wmc3_backward_workspace), WMC_EHIP.
+ * ------------------------------------------------------------------------- */
+int wmc3_backward(const float* f, const float* u0, const float* lam, int iters, float dt,
+                  const float* ckpt, int ckpt_every, const float* g_out, float* g_f, float* g_u0,
+                  float* g_lam, void* ws, size_t ws_bytes, wmc_shape3 s, void* stream);
 
 /* ---------------------------------------------------------------------------
  * wmc_workspace_bytes -- one query for every workspace size:

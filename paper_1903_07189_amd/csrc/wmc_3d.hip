@@ -142,10 +142,35 @@ __device__ __forceinline__ float select18(const Acc& a) {
     return best;
 }
 
+// The same picks as select18, also returning the 0-based index of the
+// winner (2 j for S = A - D_j, 2 j + 1 for A + D_j).
+__device__ __forceinline__ float select18_idx(const Acc& a, int& idx) {
+    const float A = __builtin_fmaf(-64.0f, a.c, a.A);
+    const float D[9] = {a.dx, a.dy, a.dz, a.dxy, a.dxmy, a.dxz, a.dxmz, a.dyz, a.dymz};
+    float best = A - D[0];
+    int bi = 0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        if (j > 0) {
+            const float lo = A - D[j];
+            const bool b0 = __builtin_fabsf(lo) < __builtin_fabsf(best);
+            best = b0 ? lo : best;
+            bi = b0 ? 2 * j : bi;
+        }
+        const float hi = A + D[j];
+        const bool b1 = __builtin_fabsf(hi) < __builtin_fabsf(best);
+        best = b1 ? hi : best;
+        bi = b1 ? 2 * j + 1 : bi;
+    }
+    idx = bi;
+    return best;
+}
+
 struct Vol3Args {
     const float* u;
     const float* f;  // data term or null
     float* out;
+    uint8_t* amap;   // selection map or null
     const float* lam;
     float dt;
     int mode;        // kModeCompute / kModeData / kModeFlow
@@ -158,49 +183,58 @@ struct Phase3 {
     static constexpr int value = P;
 };
 
-__global__ __launch_bounds__(256) void k_stream3d(Vol3Args A) {
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int64_t per_vol = (int64_t)A.nseg * A.h * A.nstrip;
-    const int64_t total = A.n * per_vol;
-    const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
-    if (item >= total) return;
-    const int v = (int)(item / per_vol);
-    int64_t rem = item - (int64_t)v * per_vol;
-    const int seg = (int)(rem / ((int64_t)A.h * A.nstrip));
-    rem -= (int64_t)seg * A.h * A.nstrip;
-    const int y = (int)(rem / A.nstrip);
-    const int strip = (int)(rem - (int64_t)y * A.nstrip);
-    const int D = (int)A.d, H = (int)A.h, W = (int)A.w;
-    const int x = strip * k3Step - k3Halo + lane;
-    const int ox1 = strip * k3Step + k3Step < W ? strip * k3Step + k3Step : W;
-    const bool own = x >= strip * k3Step && x < ox1;
-    const uint32_t xc = (uint32_t)(x < 0 ? 0 : (x < W ? x : W - 1));
-    const int z0 = seg * A.R;
-    const int z1 = z0 + A.R < D ? z0 + A.R : D;
-    const int64_t voff = (int64_t)v * A.vs;
-    const float* u = A.u + voff;
-    const float* f = A.f ? A.f + voff : nullptr;
-    float* out = A.out + voff;
-    const int64_t ym = (int64_t)(y > 0 ? y - 1 : 0) * A.ld;
-    const int64_t y0 = (int64_t)y * A.ld;
-    const int64_t yp = (int64_t)(y + 1 < H ? y + 1 : H - 1) * A.ld;
-    const bool data = A.mode == kModeData;
-    const float lam = (data && A.lam) ? A.lam[v] : 0.0f;
-    const Coef cf = make_coef(lam, A.dt, data);
-    const float lam56 = lam / 56.0f, delta56 = cf.delta / 56.0f;
+// One work item of the z-streaming kernels: volume v, row y, the lane's
+// column x (owned or a halo lane), clamped column and row offsets, and the
+// segment [z0, z1) of voxel planes.
+struct Item3 {
+    int v, y, x, z0, z1;
+    bool own;
+    uint32_t xc;
+    int64_t voff, ym, y0, yp;
+};
 
+__device__ __forceinline__ Item3 item3(int64_t item, int64_t per_vol, int nseg, int nstrip, int R,
+                                       int D, int H, int W, int64_t ld, int64_t vs) {
+    Item3 it;
+    const int lane = threadIdx.x & 63;
+    it.v = (int)(item / per_vol);
+    int64_t rem = item - (int64_t)it.v * per_vol;
+    const int seg = (int)(rem / ((int64_t)H * nstrip));
+    rem -= (int64_t)seg * H * nstrip;
+    it.y = (int)(rem / nstrip);
+    const int strip = (int)(rem - (int64_t)it.y * nstrip);
+    it.x = strip * k3Step - k3Halo + lane;
+    const int ox1 = strip * k3Step + k3Step < W ? strip * k3Step + k3Step : W;
+    it.own = it.x >= strip * k3Step && it.x < ox1;
+    it.xc = (uint32_t)(it.x < 0 ? 0 : (it.x < W ? it.x : W - 1));
+    it.z0 = seg * R;
+    it.z1 = it.z0 + R < D ? it.z0 + R : D;
+    it.voff = (int64_t)it.v * vs;
+    it.ym = (int64_t)(it.y > 0 ? it.y - 1 : 0) * ld;
+    it.y0 = (int64_t)it.y * ld;
+    it.yp = (int64_t)(it.y + 1 < H ? it.y + 1 : H - 1) * ld;
+    (void)nseg;
+    return it;
+}
+
+// Streams planes z0-1 .. z1 (clamped: the replicate border) of the volume u
+// through the accumulators and calls fin(z, acc) for every voxel z of the
+// segment once its window is complete.  f (or null): the data term, whose
+// value at the voxel is handed over in acc.f.
+template <class Fin>
+__device__ __forceinline__ void walk3(const float* u, const float* f, const Item3& it, int D,
+                                      int64_t ss, Fin&& fin) {
     struct Rows {
         float t, m, b, f;
     };
     auto fetch = [&](int p) {
         Rows r;
         const int pc = p < 0 ? 0 : (p < D ? p : D - 1);
-        const float* pl = u + (int64_t)pc * A.ss;
-        r.t = ld_at<float>(pl + ym, xc);
-        r.m = ld_at<float>(pl + y0, xc);
-        r.b = ld_at<float>(pl + yp, xc);
-        r.f = (data && p >= z0 && p < z1) ? ld_at<float>(f + (int64_t)pc * A.ss + y0, xc) : 0.0f;
+        const float* pl = u + (int64_t)pc * ss;
+        r.t = ld_at<float>(pl + it.ym, it.xc);
+        r.m = ld_at<float>(pl + it.y0, it.xc);
+        r.b = ld_at<float>(pl + it.yp, it.xc);
+        r.f = (f && p >= it.z0 && p < it.z1) ? ld_at<float>(f + (int64_t)pc * ss + it.y0, it.xc) : 0.0f;
         return r;
     };
 
@@ -208,9 +242,8 @@ __global__ __launch_bounds__(256) void k_stream3d(Vol3Args A) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) acc_zero(acc[i]);
     Rows pre[2];
-    // planes p = z0-1 .. z1 (clamped: the replicate border); voxel z is
-    // finished when plane z+1 has been added
-    int p = z0 - 1;
+    // voxel z is finished when plane z+1 has been added
+    int p = it.z0 - 1;
     pre[0] = fetch(p);
     pre[1] = fetch(p + 1);
 
@@ -227,23 +260,219 @@ __global__ __launch_bounds__(256) void k_stream3d(Vol3Args A) {
         acc[Q].f = r.f;
         start_down(acc[QP], ps);
         const int zf = p - 1;  // voxel whose window is now complete
-        if (zf >= z0 && zf < z1) {
-            const float S = select18(acc[QM]);
-            float o;
-            if (A.mode == kModeCompute) o = S * (1.0f / 56.0f);
-            else if (data) o = __builtin_fmaf(cf.delta, __builtin_fmaf(lam56, S, acc[QM].f - acc[QM].c),
-                                              acc[QM].c);
-            else o = __builtin_fmaf(delta56, S, acc[QM].c);
-            if (own) out[(int64_t)zf * A.ss + y0 + x] = o;
-        }
+        if (zf >= it.z0 && zf < it.z1) fin(zf, acc[QM]);
     };
     while (true) {
         step(Phase3<0>{});
-        if (++p > z1) break;
+        if (++p > it.z1) break;
         step(Phase3<1>{});
-        if (++p > z1) break;
+        if (++p > it.z1) break;
         step(Phase3<2>{});
-        if (++p > z1) break;
+        if (++p > it.z1) break;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_stream3d(Vol3Args A) {
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t per_vol = (int64_t)A.nseg * A.h * A.nstrip;
+    const int64_t total = A.n * per_vol;
+    const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
+    if (item >= total) return;
+    const int D = (int)A.d, H = (int)A.h, W = (int)A.w;
+    const Item3 it = item3(item, per_vol, A.nseg, A.nstrip, A.R, D, H, W, A.ld, A.vs);
+    const float* u = A.u + it.voff;
+    const bool data = A.mode == kModeData;
+    const float* f = data ? A.f + it.voff : nullptr;
+    float* out = A.out + it.voff;
+    uint8_t* amap = A.amap ? A.amap + it.voff : nullptr;
+    const float lam = (data && A.lam) ? A.lam[it.v] : 0.0f;
+    const Coef cf = make_coef(lam, A.dt, data);
+    const float lam56 = lam / 56.0f, delta56 = cf.delta / 56.0f;
+    walk3(u, f, it, D, A.ss, [&](int zf, const Acc& a) {
+        float S;
+        int idx = 0;
+        if (amap) S = select18_idx(a, idx);
+        else S = select18(a);
+        float o;
+        if (A.mode == kModeCompute) o = S * (1.0f / 56.0f);
+        else if (data) o = __builtin_fmaf(cf.delta, __builtin_fmaf(lam56, S, a.f - a.c), a.c);
+        else o = __builtin_fmaf(delta56, S, a.c);
+        if (it.own) {
+            const int64_t q = (int64_t)zf * A.ss + it.y0 + it.x;
+            out[q] = o;
+            if (amap) amap[q] = (uint8_t)idx;
+        }
+    });
+}
+
+// ---- adjoint -----------------------------------------------------------------
+// With the selection m(x) held at its forward value the update is affine in U
+// and f (U' = U + delta[(f - U) + lam/56 sum_o w_m(x)[o] Ubar(x + o)], w with
+// the centre weight -56), so its adjoint is
+//   dL/dU(v) = keep g(v) + coef sum_{x, o : clamp(x + o) = v} w_m(x)[o] g(x)
+// with keep = 1 - delta, coef = delta lam / 56 (data term) or keep = 1,
+// coef = delta / 56 (flow), dL/df += delta g and
+// dL/dlam = sum g (delta H - [delta = 1/(1+lam)] delta^2 ((f - U) + lam H)).
+// One step is two launches.  k_adjsel3d recomputes m from U^t with the
+// forward's arithmetic (bitwise the same choice, the same walk) into a byte
+// map and, with a data term, updates dL/df and writes the work item's dL/dlam
+// partial sum.  k_adjgather3d then gathers the sum for every voxel v from the
+// selections and cotangents of its 27 neighbours, the replicate border folded
+// in exactly (integer weight sums).
+
+struct Adj3Args {
+    const float* u;
+    const float* f;  // data term or null (flow)
+    const float* g;  // dL/dU^{t+1}
+    float* g_f;      // dL/df (read unless gf_first, then written) or null
+    uint8_t* sel;    // selection map out
+    float* part;     // dL/dlam partial sums (slot * items + item) or null
+    const float* lam;
+    float dt;
+    int64_t n, d, h, w, ld, ss, vs;
+    int32_t R, nstrip, nseg, slot, gf_first, dlam_default;
+};
+
+__global__ __launch_bounds__(256) void k_adjsel3d(Adj3Args A) {
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t per_vol = (int64_t)A.nseg * A.h * A.nstrip;
+    const int64_t total = A.n * per_vol;
+    const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
+    if (item >= total) return;
+    const int D = (int)A.d, H = (int)A.h, W = (int)A.w;
+    const Item3 it = item3(item, per_vol, A.nseg, A.nstrip, A.R, D, H, W, A.ld, A.vs);
+    const bool data = A.f != nullptr;
+    const float* u = A.u + it.voff;
+    const float* f = data ? A.f + it.voff : nullptr;
+    const float* g = A.g + it.voff;
+    float* gfp = (data && A.g_f) ? A.g_f + it.voff : nullptr;
+    uint8_t* sel = A.sel + it.voff;
+    const float lam = data ? A.lam[it.v] : 0.0f;
+    const Coef cf = make_coef(lam, A.dt, data);
+    float contrib = 0.0f;
+    walk3(u, f, it, D, A.ss, [&](int zf, const Acc& a) {
+        int idx;
+        const float S = select18_idx(a, idx);
+        const int64_t q = (int64_t)zf * A.ss + it.y0 + it.x;
+        if (it.own) sel[q] = (uint8_t)idx;
+        if (data) {
+            const float gv = it.own ? g[q] : 0.0f;
+            const float hd = S * (1.0f / 56.0f);
+            float dudl = cf.delta * hd;
+            if (A.dlam_default) dudl -= cf.delta * cf.delta * ((a.f - a.c) + lam * hd);
+            contrib = it.own ? __builtin_fmaf(gv, dudl, contrib) : contrib;
+            if (gfp && it.own) gfp[q] = __builtin_fmaf(cf.delta, gv, A.gf_first ? 0.0f : gfp[q]);
+        }
+    });
+    if (data && A.part) {
+        // fixed-order butterfly over the wave
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
+        if ((threadIdx.x & 63) == 0) A.part[(int64_t)A.slot * total + item] = contrib;
+    }
+}
+
+// Normals of the 9 mirror planes (x, y, z components), plane order of the
+// candidates: e_x, e_y, e_z, e_x + e_y, e_x - e_y, e_x + e_z, e_x - e_z,
+// e_y + e_z, e_y - e_z.
+__constant__ int8_t kPlaneN[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0},
+                                     {1, 0, 1}, {1, 0, -1}, {0, 1, 1}, {0, 1, -1}};
+
+// Tap o = (ox, oy, oz) of half window i (x56 domain): -56 at the centre,
+// elsewhere c[o] (1 - sign(n_j . o)) for the n.o <= 0 side (i = 2j) and
+// c[o] (1 + sign(n_j . o)) for the other (i = 2j + 1), c = s (x) s (x) s:
+// the kept side's weight doubled, the plane's kept, the other side's folded
+// away (S = A -+ D_j).
+__device__ __forceinline__ int tap3(int i, int oz, int oy, int ox) {
+    if (!ox && !oy && !oz) return -56;
+    const int c = (ox ? 1 : 2) * (oy ? 1 : 2) * (oz ? 1 : 2);
+    const int j = i >> 1;
+    const int dot = kPlaneN[j][0] * ox + kPlaneN[j][1] * oy + kPlaneN[j][2] * oz;
+    const int sg = dot > 0 ? 1 : (dot < 0 ? -1 : 0);
+    return (i & 1) ? c * (1 + sg) : c * (1 - sg);
+}
+
+struct Gather3Args {
+    const float* g;      // dL/dU^{t+1}
+    const uint8_t* sel;  // selections of step t
+    float* g_prev;       // dL/dU^t out
+    float* g_f;          // null, or dL/df to which dL/dU^t is added (U^0 = f)
+    const float* lam;
+    float dt;
+    int32_t data;
+    int64_t n, d, h, w, ld, ss, vs;
+};
+
+__device__ __forceinline__ int clamp3(int v, int n) { return v < 0 ? 0 : (v < n ? v : n - 1); }
+
+// One block per image row (volume, z, y) at a time, the threads along x.
+__global__ __launch_bounds__(256) void k_adjgather3d(Gather3Args A) {
+    __shared__ int tab[18 * 27];  // tab[i * 27 + (oz+1)*9 + (oy+1)*3 + (ox+1)]
+    for (int t = threadIdx.x; t < 18 * 27; t += 256) {
+        const int o = t % 27;
+        tab[t] = tap3(t / 27, o / 9 - 1, (o / 3) % 3 - 1, o % 3 - 1);
+    }
+    __syncthreads();
+    const int D = (int)A.d, H = (int)A.h, W = (int)A.w;
+    const int64_t rows = A.n * A.d * A.h;
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int y = (int)(r % H);
+        const int64_t zv = r / H;
+        const int z = (int)(zv % D);
+        const int v = (int)(zv / D);
+        const int64_t base = (int64_t)v * A.vs;
+        const bool data = A.data != 0;
+        const float lam = data ? A.lam[v] : 0.0f;
+        const Coef cf = make_coef(lam, A.dt, data);
+        const float keep = data ? 1.0f - cf.delta : 1.0f;
+        const float coef = data ? cf.delta * (lam / 56.0f) : cf.delta / 56.0f;
+        const bool zyin = z > 0 && z < D - 1 && y > 0 && y < H - 1;
+        for (int x = threadIdx.x; x < W; x += 256) {
+            float acc = 0.0f;
+            if (zyin && x > 0 && x < W - 1) {
+                // interior: the one tap o = -(dz, dy, dx) of each neighbour
+#pragma unroll
+                for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+                    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int64_t q = base + (int64_t)(z + dz) * A.ss + (int64_t)(y + dy) * A.ld + x + dx;
+                            const int wgt = tab[A.sel[q] * 27 + 13 - (dz * 9 + dy * 3 + dx)];
+                            acc = __builtin_fmaf((float)wgt, A.g[q], acc);
+                        }
+            } else {
+                // border: every tap o of a neighbour x' with clamp(x' + o) = v
+                for (int dz = -1; dz <= 1; ++dz) {
+                    const int zz = z + dz;
+                    if (zz < 0 || zz >= D) continue;
+                    for (int dy = -1; dy <= 1; ++dy) {
+                        const int yy = y + dy;
+                        if (yy < 0 || yy >= H) continue;
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int xx = x + dx;
+                            if (xx < 0 || xx >= W) continue;
+                            const int64_t q = base + (int64_t)zz * A.ss + (int64_t)yy * A.ld + xx;
+                            const int* tw = tab + A.sel[q] * 27;
+                            int wsum = 0;
+                            for (int oz = -1; oz <= 1; ++oz) {
+                                if (clamp3(zz + oz, D) != z) continue;
+                                for (int oy = -1; oy <= 1; ++oy) {
+                                    if (clamp3(yy + oy, H) != y) continue;
+                                    for (int ox = -1; ox <= 1; ++ox)
+                                        if (clamp3(xx + ox, W) == x) wsum += tw[(oz + 1) * 9 + (oy + 1) * 3 + ox + 1];
+                                }
+                            }
+                            acc = __builtin_fmaf((float)wsum, A.g[q], acc);
+                        }
+                    }
+                }
+            }
+            const int64_t o = base + (int64_t)z * A.ss + (int64_t)y * A.ld + x;
+            const float gp = __builtin_fmaf(coef, acc, keep * A.g[o]);
+            A.g_prev[o] = gp;
+            if (A.g_f) A.g_f[o] += gp;
+        }
     }
 }
 
@@ -259,11 +488,12 @@ static int vol_rows(int64_t n, int64_t d, int64_t h, int64_t strips) {
 
 hipError_t launch_stream3d(const float* u, const float* f, float* out, const float* lam, float dt,
                            int mode, int64_t n, int64_t d, int64_t h, int64_t w, int64_t ld,
-                           int64_t ss, int64_t vs, hipStream_t st) {
+                           int64_t ss, int64_t vs, hipStream_t st, uint8_t* amap) {
     Vol3Args a{};
     a.u = u;
     a.f = f;
     a.out = out;
+    a.amap = amap;
     a.lam = lam;
     a.dt = dt;
     a.mode = mode;
@@ -279,6 +509,67 @@ hipError_t launch_stream3d(const float* u, const float* f, float* out, const flo
     a.nseg = (int)((d + a.R - 1) / a.R);
     const int64_t total = n * (int64_t)a.nseg * h * a.nstrip;
     hipLaunchKernelGGL(k_stream3d, dim3((unsigned)((total + 3) / 4)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+int64_t adjsel3_items(int64_t n, int64_t d, int64_t h, int64_t w) {
+    const int nstrip = (int)((w + k3Step - 1) / k3Step);
+    const int R = vol_rows(n, d, h, nstrip);
+    return n * ((d + R - 1) / R) * h * nstrip;
+}
+
+hipError_t launch_adjsel3d(const float* u, const float* f, const float* g, float* g_f, uint8_t* sel,
+                           float* part, int slot, bool gf_first, const float* lam, float dt,
+                           int64_t n, int64_t d, int64_t h, int64_t w, int64_t ld, int64_t ss,
+                           int64_t vs, hipStream_t st) {
+    Adj3Args a{};
+    a.u = u;
+    a.f = f;
+    a.g = g;
+    a.g_f = g_f;
+    a.sel = sel;
+    a.part = part;
+    a.lam = lam;
+    a.dt = dt;
+    a.n = n;
+    a.d = d;
+    a.h = h;
+    a.w = w;
+    a.ld = ld;
+    a.ss = ss;
+    a.vs = vs;
+    a.nstrip = (int)((w + k3Step - 1) / k3Step);
+    a.R = vol_rows(n, d, h, a.nstrip);
+    a.nseg = (int)((d + a.R - 1) / a.R);
+    a.slot = slot;
+    a.gf_first = gf_first ? 1 : 0;
+    a.dlam_default = !(dt > 0.0f);
+    const int64_t total = n * (int64_t)a.nseg * h * a.nstrip;
+    hipLaunchKernelGGL(k_adjsel3d, dim3((unsigned)((total + 3) / 4)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjgather3d(const float* g, const uint8_t* sel, float* g_prev, float* g_f,
+                              const float* lam, float dt, bool data, int64_t n, int64_t d, int64_t h,
+                              int64_t w, int64_t ld, int64_t ss, int64_t vs, hipStream_t st) {
+    Gather3Args a{};
+    a.g = g;
+    a.sel = sel;
+    a.g_prev = g_prev;
+    a.g_f = g_f;
+    a.lam = lam;
+    a.dt = dt;
+    a.data = data ? 1 : 0;
+    a.n = n;
+    a.d = d;
+    a.h = h;
+    a.w = w;
+    a.ld = ld;
+    a.ss = ss;
+    a.vs = vs;
+    const int64_t rows = n * d * h;
+    const int64_t blocks = rows < ((int64_t)1 << 20) ? rows : ((int64_t)1 << 20);
+    hipLaunchKernelGGL(k_adjgather3d, dim3((unsigned)blocks), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -1735,7 +1735,7 @@ int wmc3_compute(const float* u, float* hw, wmc_shape3 s, void* stream) {
 }
 
 int wmc3_step(const float* u, const float* f, float* u_out, const float* lam, float dt,
-              wmc_shape3 s, void* stream) {
+              uint8_t* argmin_out, wmc_shape3 s, void* stream) {
     g_err.clear();
     int rc = check_shape3(s);
     if (rc) return rc;
@@ -1743,14 +1743,16 @@ int wmc3_step(const float* u, const float* f, float* u_out, const float* lam, fl
     if (f && !lam) return fail(WMC_EINVAL, "wmc3_step: lam is required with a data term");
     if (!std::isfinite(dt)) return fail(WMC_EINVAL, "wmc3_step: dt must be finite");
     const int64_t ext = extent3(s);
-    const Range ro = range_of(u_out, ext, 4);
-    if (overlaps(ro, range_of(u, ext, 4)) || overlaps(ro, range_of(f, ext, 4)))
+    const Range ro = range_of(u_out, ext, 4), ra = range_of(argmin_out, ext, 1);
+    if (overlaps(ro, range_of(u, ext, 4)) || overlaps(ro, range_of(f, ext, 4)) || overlaps(ro, ra))
         return fail(WMC_EINVAL, "wmc3_step: u_out overlaps an input (updates are synchronous)");
+    if (overlaps(ra, range_of(u, ext, 4)) || overlaps(ra, range_of(f, ext, 4)))
+        return fail(WMC_EINVAL, "wmc3_step: argmin_out overlaps an input");
     int dev;
     rc = check_device(&dev);
     if (rc) return rc;
     const hipError_t e = launch_stream3d(u, f, u_out, lam, dt, f ? kModeData : kModeFlow, s.n, s.d,
-                                         s.h, s.w, s.ld, s.ss, s.vs, as_stream(stream));
+                                         s.h, s.w, s.ld, s.ss, s.vs, as_stream(stream), argmin_out);
     return e == hipSuccess ? WMC_OK : hip_fail(e, "wmc3_step launch");
 }
 
@@ -1759,8 +1761,42 @@ size_t wmc3_solve_workspace(wmc_shape3 s) {
     return (size_t)set_stride3(s) * sizeof(float);
 }
 
+int64_t wmc3_set_stride(wmc_shape3 s) {
+    if (check_shape3(s)) return 0;
+    return set_stride3(s);
+}
+
+namespace {
+
+// Copies every volume of src to dst (layout s).
+hipError_t copy_volumes(const float* src, float* dst, const wmc_shape3& s, hipStream_t st) {
+    for (int64_t v = 0; v < s.n; ++v) {
+        const hipError_t e = launch_copy_planes(src + v * s.vs, dst + v * s.vs, s.d, s.h, s.w, s.ld,
+                                                s.ss, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Output buffer of each of `iters` single-sweep launches: u_out for the
+// last, the checkpoint slot for a state that is one, otherwise ws or u_out
+// alternately so that no launch writes the buffer it reads.
+std::vector<float*> sweep_targets3(int iters, float* u_out, float* ws, float* ckpt, int ckpt_every,
+                                   int64_t set) {
+    std::vector<float*> dst(iters);
+    for (int t = iters - 1; t >= 0; --t) {
+        if (t == iters - 1) dst[t] = u_out;
+        else if (ckpt && (t + 1) % ckpt_every == 0) dst[t] = ckpt + (int64_t)((t + 1) / ckpt_every) * set;
+        else dst[t] = (dst[t + 1] == u_out) ? ws : u_out;
+    }
+    return dst;
+}
+
+}  // namespace
+
 int wmc3_solve(const float* f, const float* u0, float* u_out, const float* lam, int iters,
-               float dt, void* ws, size_t ws_bytes, wmc_shape3 s, void* stream) {
+               float dt, float* ckpt, int ckpt_every, void* ws, size_t ws_bytes, wmc_shape3 s,
+               void* stream) {
     g_err.clear();
     int rc = check_shape3(s);
     if (rc) return rc;
@@ -1768,34 +1804,164 @@ int wmc3_solve(const float* f, const float* u0, float* u_out, const float* lam, 
     if (!f && !u0) return fail(WMC_EINVAL, "wmc3_solve: the flow (f == NULL) needs u0");
     if (f && !lam) return fail(WMC_EINVAL, "wmc3_solve: lam is required with a data term");
     if (iters < 0 || !std::isfinite(dt)) return fail(WMC_EINVAL, "wmc3_solve: bad iters or dt");
-    const int64_t ext = extent3(s);
+    if (ckpt && ckpt_every < 1) return fail(WMC_EINVAL, "wmc3_solve: ckpt_every must be >= 1");
+    const int64_t ext = extent3(s), set = set_stride3(s);
     if (iters >= 2 && (!ws || ws_bytes < wmc3_solve_workspace(s)))
         return fail(WMC_ENOMEM, "wmc3_solve: workspace smaller than wmc3_solve_workspace()");
     const float* src0 = u0 ? u0 : f;
+    const int64_t nck = ckpt ? wmc_num_checkpoints(iters, ckpt_every) : 0;
     const Range ro = range_of(u_out, ext, 4), rw = range_of(iters >= 2 ? ws : nullptr, ext, 4);
+    const Range rc_ = range_of(ckpt, nck > 0 ? (nck - 1) * set + ext : 0, 4);
     for (const Range& r : {range_of(src0, ext, 4), range_of(f, ext, 4)})
-        if (overlaps(ro, r) || overlaps(rw, r)) return fail(WMC_EINVAL, "wmc3_solve: buffers overlap");
-    if (overlaps(ro, rw)) return fail(WMC_EINVAL, "wmc3_solve: u_out overlaps ws");
+        if (overlaps(ro, r) || overlaps(rw, r) || overlaps(rc_, r))
+            return fail(WMC_EINVAL, "wmc3_solve: buffers overlap");
+    if (overlaps(ro, rw) || overlaps(rc_, ro) || overlaps(rc_, rw))
+        return fail(WMC_EINVAL, "wmc3_solve: u_out, ws and ckpt must not overlap");
     int dev;
     rc = check_device(&dev);
     if (rc) return rc;
     hipStream_t st = as_stream(stream);
+    if (nck > 0) {
+        const hipError_t e = copy_volumes(src0, ckpt, s, st);  // checkpoint 0 = U^0
+        if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+    }
     if (iters == 0) {
-        // copy each volume's slices row by row
-        for (int64_t v = 0; v < s.n; ++v) {
-            const hipError_t e = launch_copy_planes(src0 + v * s.vs, u_out + v * s.vs, s.d, s.h, s.w,
-                                                    s.ld, s.ss, st);
+        const hipError_t e = copy_volumes(src0, u_out, s, st);
+        return e == hipSuccess ? WMC_OK : hip_fail(e, "copy");
+    }
+    const std::vector<float*> dst =
+        sweep_targets3(iters, u_out, static_cast<float*>(ws), nck > 0 ? ckpt : nullptr, ckpt_every, set);
+    const float* src = src0;
+    for (int t = 0; t < iters; ++t) {
+        const hipError_t e = launch_stream3d(src, f, dst[t], lam, dt, f ? kModeData : kModeFlow, s.n,
+                                             s.d, s.h, s.w, s.ld, s.ss, s.vs, st);
+        if (e != hipSuccess) return hip_fail(e, "wmc3_solve launch");
+        src = dst[t];
+    }
+    return WMC_OK;
+}
+
+size_t wmc3_backward_workspace(wmc_shape3 s, int iters, int ckpt_every) {
+    if (check_shape3(s) || iters < 0 || ckpt_every < 1) return 0;
+    const size_t set = (size_t)set_stride3(s) * sizeof(float);
+    const int c = std::min(ckpt_every, std::max(iters, 1));
+    const size_t states = (size_t)std::max(c - 1, 0) * set;
+    const size_t grads = 2 * set;
+    const size_t sel = ((size_t)set_stride3(s) + 255) / 256 * 256;  // one byte per voxel
+    const int G = lam_slots(iters, c);
+    const size_t part = ((size_t)G * (size_t)adjsel3_items(s.n, s.d, s.h, s.w) * sizeof(float) + 255) /
+                        256 * 256;
+    const size_t sums = (size_t)s.n * G * sizeof(float);
+    return states + grads + sel + part + sums;
+}
+
+int wmc3_backward(const float* f, const float* u0, const float* lam, int iters, float dt,
+                  const float* ckpt, int ckpt_every, const float* g_out, float* g_f, float* g_u0,
+                  float* g_lam, void* ws, size_t ws_bytes, wmc_shape3 s, void* stream) {
+    g_err.clear();
+    int rc = check_shape3(s);
+    if (rc) return rc;
+    if (!f && !u0) return fail(WMC_EINVAL, "wmc3_backward: the flow needs u0");
+    if (f && !lam) return fail(WMC_EINVAL, "wmc3_backward: lam is required with a data term");
+    if (iters < 0 || ckpt_every < 1) return fail(WMC_EINVAL, "wmc3_backward: bad iters / ckpt_every");
+    if (iters > 0 && !ckpt) return fail(WMC_EINVAL, "wmc3_backward: checkpoints are required");
+    if (!g_out) return fail(WMC_EINVAL, "wmc3_backward: null g_out");
+    if (!std::isfinite(dt)) return fail(WMC_EINVAL, "wmc3_backward: dt must be finite");
+    const size_t need = wmc3_backward_workspace(s, iters, ckpt_every);
+    if (!ws || ws_bytes < need) return fail(WMC_ENOMEM, "wmc3_backward: workspace too small");
+    const int64_t ext = extent3(s), set = set_stride3(s);
+    const Range rw = range_of(ws, (int64_t)need, 1), rg = range_of(g_out, ext, 4);
+    for (const void* p : {(const void*)g_f, (const void*)g_u0})
+        if (p && (overlaps(range_of(p, ext, 4), rw) || overlaps(range_of(p, ext, 4), rg)))
+            return fail(WMC_EINVAL, "wmc3_backward: outputs overlap the workspace or g_out");
+    if (g_f && g_u0 && overlaps(range_of(g_f, ext, 4), range_of(g_u0, ext, 4)))
+        return fail(WMC_EINVAL, "wmc3_backward: g_f and g_u0 overlap");
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t st = as_stream(stream);
+    const bool data = f != nullptr;
+    const int c = std::min(ckpt_every, std::max(iters, 1));
+    char* w = static_cast<char*>(ws);
+    float* states = reinterpret_cast<float*>(w);
+    w += (size_t)std::max(c - 1, 0) * set * sizeof(float);
+    float* gbuf[2] = {reinterpret_cast<float*>(w), reinterpret_cast<float*>(w) + set};
+    w += 2 * set * sizeof(float);
+    uint8_t* sel = reinterpret_cast<uint8_t*>(w);
+    w += ((size_t)set + 255) / 256 * 256;
+    const int G = lam_slots(iters, c);
+    const int64_t items = adjsel3_items(s.n, s.d, s.h, s.w);
+    float* part = reinterpret_cast<float*>(w);
+    w += ((size_t)G * (size_t)items * sizeof(float) + 255) / 256 * 256;
+    float* lam_sums = reinterpret_cast<float*>(w);
+    float* apart = (data && g_lam) ? part : nullptr;
+    hipError_t e;
+    bool lam_first = true;
+    if (g_lam && !(apart && iters >= 1)) {
+        e = launch_fill_f32(g_lam, s.n, 0.0f, st);
+        if (e != hipSuccess) return hip_fail(e, "fill");
+    }
+    if (iters == 0) {
+        if (g_u0) {
+            e = copy_volumes(g_out, g_u0, s, st);
+            if (e != hipSuccess) return hip_fail(e, "copy");
+        }
+        if (data && g_f) {
+            // dL/df = dL/dU^0 when U^0 = f, else zero
+            if (!u0) e = copy_volumes(g_out, g_f, s, st);
+            else
+                for (int64_t v = 0; v < s.n && e == hipSuccess; ++v)
+                    for (int64_t z = 0; z < s.d && e == hipSuccess; ++z)
+                        e = launch_fill_f32(g_f + v * s.vs + z * s.ss, (s.h - 1) * s.ld + s.w, 0.0f, st);
             if (e != hipSuccess) return hip_fail(e, "copy");
         }
         return WMC_OK;
     }
-    const float* src = src0;
-    for (int t = 0; t < iters; ++t) {
-        float* dst = ((iters - 1 - t) % 2 == 0) ? u_out : static_cast<float*>(ws);
-        const hipError_t e = launch_stream3d(src, f, dst, lam, dt, f ? kModeData : kModeFlow, s.n,
-                                             s.d, s.h, s.w, s.ld, s.ss, s.vs, st);
-        if (e != hipSuccess) return hip_fail(e, "wmc3_solve launch");
-        src = dst;
+    const float* gcur = g_out;
+    int gnext = 0;
+    int left = iters;
+    int used = 0;
+    bool gf_first = true;
+    const int nseg = (int)wmc_num_checkpoints(iters, ckpt_every);
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int t0 = sg * ckpt_every;
+        const int t1 = std::min(t0 + ckpt_every, iters);
+        std::vector<const float*> ust(t1 - t0);
+        ust[0] = ckpt + (int64_t)sg * set;
+        // recompute the segment's states, one sweep per launch (bitwise those of the solve)
+        for (int j = 1; j < t1 - t0; ++j) {
+            float* dst = states + (int64_t)(j - 1) * set;
+            e = launch_stream3d(ust[j - 1], f, dst, lam, dt, data ? kModeData : kModeFlow, s.n, s.d,
+                                s.h, s.w, s.ld, s.ss, s.vs, st);
+            if (e != hipSuccess) return hip_fail(e, "recompute launch");
+            ust[j] = dst;
+        }
+        for (int t = t1 - 1; t >= t0; --t) {
+            float* dst = (left == 1 && g_u0) ? g_u0 : gbuf[gnext];
+            e = launch_adjsel3d(ust[t - t0], f, gcur, data ? g_f : nullptr, sel, apart, G - 1 - used,
+                                gf_first, lam, dt, s.n, s.d, s.h, s.w, s.ld, s.ss, s.vs, st);
+            if (e != hipSuccess) return hip_fail(e, "adjoint selection launch");
+            gf_first = false;
+            // the last step also adds dL/dU^0 into dL/df when U^0 = f
+            float* fold = (left == 1 && data && g_f && !u0) ? g_f : nullptr;
+            e = launch_adjgather3d(gcur, sel, dst, fold, lam, dt, data, s.n, s.d, s.h, s.w, s.ld, s.ss,
+                                   s.vs, st);
+            if (e != hipSuccess) return hip_fail(e, "adjoint gather launch");
+            if (dst == gbuf[gnext]) gnext ^= 1;
+            gcur = dst;
+            --left;
+            if (apart && ++used == G) {
+                e = launch_lambda_reduce(part, G, items, items / s.n, s.n, lam_first, g_lam, lam_sums, st);
+                if (e != hipSuccess) return hip_fail(e, "lambda reduction");
+                lam_first = false;
+                used = 0;
+            }
+        }
+    }
+    if (apart && used > 0) {
+        e = launch_lambda_reduce(part + (int64_t)(G - used) * items, used, items, items / s.n, s.n,
+                                 lam_first, g_lam, lam_sums, st);
+        if (e != hipSuccess) return hip_fail(e, "lambda reduction");
     }
     return WMC_OK;
 }

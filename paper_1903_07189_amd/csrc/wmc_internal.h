@@ -164,10 +164,23 @@ hipError_t launch_layer_backward(const float* u, const float* w, int K, const ui
                                  const float* g, float* g_u, float* part, float* g_w, int64_t n,
                                  int64_t h, int64_t wd, int64_t ld, int64_t ps, hipStream_t st);
 
-// 3-D volumes (wmc_3d.hip).
+// 3-D volumes (wmc_3d.hip).  amap: null, or the selection map (1 byte per
+// voxel, the layout of the volumes).
 hipError_t launch_stream3d(const float* u, const float* f, float* out, const float* lam, float dt,
                            int mode, int64_t n, int64_t d, int64_t h, int64_t w, int64_t ld,
-                           int64_t ss, int64_t vs, hipStream_t st);
+                           int64_t ss, int64_t vs, hipStream_t st, uint8_t* amap = nullptr);
+// Adjoint of one 3-D step: the selection pass (selection map, dL/df, the
+// dL/dlam partial sum of each of adjsel3_items() work items at
+// part + slot * items) and the gather of dL/dU^t (with g_f set, dL/dU^t is
+// also added into it).
+int64_t adjsel3_items(int64_t n, int64_t d, int64_t h, int64_t w);
+hipError_t launch_adjsel3d(const float* u, const float* f, const float* g, float* g_f, uint8_t* sel,
+                           float* part, int slot, bool gf_first, const float* lam, float dt,
+                           int64_t n, int64_t d, int64_t h, int64_t w, int64_t ld, int64_t ss,
+                           int64_t vs, hipStream_t st);
+hipError_t launch_adjgather3d(const float* g, const uint8_t* sel, float* g_prev, float* g_f,
+                              const float* lam, float dt, bool data, int64_t n, int64_t d, int64_t h,
+                              int64_t w, int64_t ld, int64_t ss, int64_t vs, hipStream_t st);
 
 // Auxiliary kernels (wmc_aux.hip).
 hipError_t launch_fd(const float* u, float* out, int64_t n, int64_t h, int64_t w, int64_t ld,

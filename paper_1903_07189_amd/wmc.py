@@ -59,7 +59,8 @@ EXPORTS = ["wmc_compute", "wmc_step", "wmc_solve_workspace", "wmc_set_stride",
            "wmc_num_checkpoints", "wmc_solve", "wmc_solve_noalloc", "wmc_solve_tuning", "wmc_l1_workspace",
            "wmc_solve_l1", "wmc_fd_compute", "wmc_fd_flow", "wmc_layer_workspace",
            "wmc_layer_forward", "wmc_layer_backward", "wmc_workspace_bytes",
-           "wmc3_compute", "wmc3_step", "wmc3_solve_workspace", "wmc3_solve",
+           "wmc3_compute", "wmc3_step", "wmc3_solve_workspace", "wmc3_set_stride", "wmc3_solve",
+           "wmc3_backward_workspace", "wmc3_backward",
            "wmc_batched_workspace", "wmc_solve_batched", "wmc_autotune", "wmc_backward_workspace",
            "wmc_backward", "wmc_bw_probe", "wmc_selftest", "wmc_last_error", "wmc_release"]
 
@@ -91,10 +92,15 @@ def lib():
     L.wmc_fd_compute.argtypes = [P, P, F, Shape, P]
     L.wmc_fd_flow.argtypes = [P, P, I, F, F, P, SZ, Shape, P]
     L.wmc3_compute.argtypes = [P, P, Shape3, P]
-    L.wmc3_step.argtypes = [P, P, P, P, F, Shape3, P]
+    L.wmc3_step.argtypes = [P, P, P, P, F, P, Shape3, P]
     L.wmc3_solve_workspace.argtypes = [Shape3]
     L.wmc3_solve_workspace.restype = SZ
-    L.wmc3_solve.argtypes = [P, P, P, P, I, F, P, SZ, Shape3, P]
+    L.wmc3_set_stride.argtypes = [Shape3]
+    L.wmc3_set_stride.restype = I64
+    L.wmc3_solve.argtypes = [P, P, P, P, I, F, P, I, P, SZ, Shape3, P]
+    L.wmc3_backward_workspace.argtypes = [Shape3, I, I]
+    L.wmc3_backward_workspace.restype = SZ
+    L.wmc3_backward.argtypes = [P, P, P, I, F, P, I, P, P, P, P, P, SZ, Shape3, P]
     L.wmc_workspace_bytes.argtypes = [I, Shape, I, I]
     L.wmc_workspace_bytes.restype = SZ
     L.wmc_layer_workspace.argtypes = [Shape, I]
@@ -118,7 +124,7 @@ def lib():
     for name in ("wmc_compute", "wmc_step", "wmc_solve", "wmc_solve_noalloc", "wmc_solve_tuning",
                  "wmc_solve_l1",
                  "wmc_fd_compute", "wmc_fd_flow", "wmc_layer_forward", "wmc_layer_backward",
-                 "wmc3_compute", "wmc3_step", "wmc3_solve",
+                 "wmc3_compute", "wmc3_step", "wmc3_solve", "wmc3_backward",
                  "wmc_solve_batched",
                  "wmc_autotune",
                  "wmc_backward", "wmc_bw_probe", "wmc_selftest"):
@@ -424,9 +430,30 @@ def compute3(u: torch.Tensor) -> torch.Tensor:
     return out[0] if squeeze else out
 
 
+def step3(u: torch.Tensor, f: torch.Tensor | None = None, lam=1.0, dt: float = 0.0,
+          return_argmin: bool = False):
+    """One Jacobi update on volumes (f given: data term, else the flow); with
+    return_argmin also the selected half window of every voxel (uint8)."""
+    squeeze = u.dim() == 3
+    u = _volumes(u)
+    f = None if f is None else _volumes(f)
+    require_shape(f, u.shape, "f")
+    out = torch.empty_like(u)
+    am = torch.empty(u.shape, dtype=torch.uint8, device=u.device) if return_argmin else None
+    lt = _lam_tensor(lam, u.shape[0], u.device) if f is not None else None
+    check(lib().wmc3_step(_ptr(u), _ptr(f), _ptr(out), _ptr(lt), float(dt), _ptr(am), shape3_of(u),
+                          _stream()))
+    if squeeze:
+        out = out[0]
+        am = None if am is None else am[0]
+    return (out, am) if return_argmin else out
+
+
 def solve3(f: torch.Tensor | None, lam=1.0, iters: int = 1, dt: float = 0.0,
-           u0: torch.Tensor | None = None) -> torch.Tensor:
-    """iters Jacobi updates of the data (f given) or flow iteration on volumes."""
+           u0: torch.Tensor | None = None, ckpt_every: int | None = None):
+    """iters Jacobi updates of the data (f given) or flow iteration on volumes.
+    With ckpt_every also returns the checkpoints (num_ckpt, N, D, H, W) that
+    backward3() restarts from."""
     ref = f if f is not None else u0
     if ref is None:
         raise ValueError("need f or u0")
@@ -435,14 +462,57 @@ def solve3(f: torch.Tensor | None, lam=1.0, iters: int = 1, dt: float = 0.0,
     f = None if f is None else _volumes(f)
     u0 = None if u0 is None else _volumes(u0)
     require_shape(u0, ref.shape, "u0")
+    require_shape(f, ref.shape, "f")
     s = shape3_of(ref)
     L = lib()
     out = torch.empty_like(ref)
     ws = torch.empty(max(1, L.wmc3_solve_workspace(s) // 4), dtype=torch.float32, device=ref.device)
     lt = _lam_tensor(lam, ref.shape[0], ref.device) if f is not None else None
-    check(L.wmc3_solve(_ptr(f), _ptr(u0), _ptr(out), _ptr(lt), int(iters), float(dt), _ptr(ws),
-                       ws.numel() * 4, s, _stream()))
-    return out[0] if squeeze else out
+    ck = None
+    if ckpt_every:
+        if L.wmc3_set_stride(s) != ref.numel():
+            raise ValueError("checkpointing needs a contiguous volume set")
+        ck = torch.empty((checkpoint_sets(iters, ckpt_every),) + tuple(ref.shape),
+                         dtype=torch.float32, device=ref.device)
+    check(L.wmc3_solve(_ptr(f), _ptr(u0), _ptr(out), _ptr(lt), int(iters), float(dt), _ptr(ck),
+                       int(ckpt_every or 0), _ptr(ws), ws.numel() * 4, s, _stream()))
+    if squeeze:
+        out = out[0]
+    return (out, ck) if ckpt_every else out
+
+
+def backward3(g_out: torch.Tensor, f: torch.Tensor | None, lam, iters: int, ckpt: torch.Tensor,
+              ckpt_every: int, dt: float = 0.0, u0: torch.Tensor | None = None):
+    """Reverse-mode derivative of L(U^iters) through solve3(); returns
+    (g_f, g_u0, g_lam) for (N, D, H, W) volumes.  g_f includes the path
+    through U^0 = f when u0 is None."""
+    ref = f if f is not None else u0
+    if ref is None:
+        raise ValueError("need f or u0")
+    ref = _volumes(ref)
+    f = None if f is None else _volumes(f)
+    u0 = None if u0 is None else _volumes(u0)
+    g_out = _volumes(g_out)
+    require_shape(u0, ref.shape, "u0")
+    require_shape(g_out, ref.shape, "g_out")
+    if ckpt is None:
+        raise ValueError("backward3 needs the checkpoints of the forward solve")
+    if ckpt.dtype != torch.float32 or not ckpt.is_cuda or not ckpt.is_contiguous():
+        raise ValueError("ckpt must be a contiguous float32 CUDA tensor")
+    require_shape(ckpt, (checkpoint_sets(iters, ckpt_every),) + tuple(ref.shape), "ckpt")
+    s = shape3_of(ref)
+    L = lib()
+    n = ref.shape[0]
+    lt = _lam_tensor(lam, n, ref.device) if f is not None else None
+    ws = torch.empty(max(1, L.wmc3_backward_workspace(s, int(iters), int(ckpt_every)) // 4 + 64),
+                     dtype=torch.float32, device=ref.device)
+    g_f = torch.empty_like(ref) if f is not None else None
+    g_u0 = torch.empty_like(ref)
+    g_lam = torch.empty(n, dtype=torch.float32, device=ref.device) if f is not None else None
+    check(L.wmc3_backward(_ptr(f), _ptr(u0), _ptr(lt), int(iters), float(dt), _ptr(ckpt),
+                          int(ckpt_every), _ptr(g_out), _ptr(g_f), _ptr(g_u0), _ptr(g_lam),
+                          _ptr(ws), ws.numel() * 4, s, _stream()))
+    return g_f, g_u0, g_lam
 
 
 def solve_tuning(f: torch.Tensor | None, lam=1.0, dt: float = 0.0, u0: torch.Tensor | None = None):
@@ -623,6 +693,39 @@ def default_ckpt_every(K: int, plane_set_bytes: int) -> int:
     if K * int(plane_set_bytes) <= KEEP_ALL_STATES_BYTES:
         return 1
     return max(1, math.ceil(math.sqrt(K)))
+
+
+class WMCSolve3(torch.autograd.Function):
+    """U^K = solve3(f, lam, K) on (N, D, H, W) volumes as a differentiable
+    layer: the forward stores a checkpoint every ckpt_every steps (default
+    default_ckpt_every), the backward runs the hand-written 3-D adjoint.
+    Gradients flow to f and to lam (N,)."""
+
+    @staticmethod
+    def forward(ctx, f, lam, K: int, dt: float = 0.0, ckpt_every: int | None = None):
+        K = int(K)
+        c = int(ckpt_every) if ckpt_every else default_ckpt_every(K, f.numel() * 4)
+        fv = _volumes(f.detach())
+        lam_t = _lam_tensor(lam, fv.shape[0], f.device)
+        out, ck = solve3(fv, lam_t, K, dt=dt, ckpt_every=c)
+        ctx.save_for_backward(fv, lam_t, ck)
+        ctx.K, ctx.c, ctx.dt = K, c, float(dt)
+        ctx.f_shape = tuple(f.shape)
+        ctx.lam_is_tensor = isinstance(lam, torch.Tensor)
+        ctx.lam_shape = tuple(lam.shape) if ctx.lam_is_tensor else None
+        ctx.lam_numel = lam.numel() if ctx.lam_is_tensor else 0
+        return out.reshape(f.shape)
+
+    @staticmethod
+    def backward(ctx, g):
+        f, lam_t, ck = ctx.saved_tensors
+        g_f, _, g_lam = backward3(g.reshape(f.shape).contiguous(), f, lam_t, ctx.K, ck, ctx.c,
+                                  dt=ctx.dt)
+        gl = None
+        if ctx.lam_is_tensor:
+            gl = g_lam.reshape(ctx.lam_shape) if ctx.lam_numel == g_lam.numel() else \
+                g_lam.sum().reshape(ctx.lam_shape)
+        return g_f.reshape(ctx.f_shape), gl, None, None, None
 
 
 class WMCSolve(torch.autograd.Function):

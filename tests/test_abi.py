@@ -152,6 +152,43 @@ def test_backward_validation(wmc):
     assert "ld" in L.wmc_last_error().decode()
 
 
+def test_volume_solve_and_backward_validation(wmc):
+    """The 3-D checkpointed solve and the 3-D backward reject bad arguments
+    on the host; their workspace queries follow the volume layout."""
+    L = wmc.lib()
+    S3 = wmc.Shape3
+    s = S3(2, 5, 6, 7, 8, 6 * 8, 5 * 6 * 8)
+    set3 = 2 * 5 * 6 * 8
+    assert L.wmc3_set_stride(s) == set3
+    assert L.wmc3_set_stride(S3(1, 5, 6, 7, 8, 6 * 8, 0)) == 4 * 48 + 5 * 8 + 7
+    assert L.wmc3_set_stride(S3(0, 5, 6, 7, 8, 48, 240)) == 0
+    ws = L.wmc3_backward_workspace(s, 6, 3)
+    # two recomputed states, two cotangents, a byte map, lambda partials
+    assert ws >= (2 + 2) * set3 * 4 + set3
+    assert L.wmc3_backward_workspace(s, 6, 0) == 0
+    assert L.wmc3_backward_workspace(s, -1, 2) == 0
+    # solve: ckpt_every < 1 with checkpoints, checkpoints overlapping u_out
+    assert L.wmc3_solve(P(4096), None, P(1 << 20), P(64), 6, 0.0, P(1 << 22), 0, P(1 << 21),
+                        1 << 16, s, None) == wmc.WMC_EINVAL
+    assert L.wmc3_solve(P(4096), None, P(1 << 20), P(64), 6, 0.0, P(1 << 20), 3, P(1 << 21),
+                        1 << 16, s, None) == wmc.WMC_EINVAL
+    # step: the selection map must not overlap the output
+    assert L.wmc3_step(P(4096), None, P(1 << 20), None, 0.5, P(1 << 20), s, None) == wmc.WMC_EINVAL
+    # backward: no checkpoints, small workspace, overlapping outputs, flow without u0
+    assert L.wmc3_backward(P(4096), None, P(64), 5, 0.0, None, 2, P(1 << 20), P(1 << 21), None,
+                           None, P(1 << 22), 1 << 24, s, None) == wmc.WMC_EINVAL
+    assert L.wmc3_backward(P(4096), None, P(64), 5, 0.0, P(1 << 23), 2, P(1 << 20), P(1 << 21),
+                           None, None, P(1 << 22), 8, s, None) == wmc.WMC_ENOMEM
+    need = L.wmc3_backward_workspace(s, 5, 2)
+    assert L.wmc3_backward(P(4096), None, P(64), 5, 0.0, P(1 << 23), 2, P(1 << 20), P(1 << 21),
+                           P(1 << 21), None, P(1 << 24), need, s, None) == wmc.WMC_EINVAL
+    assert "overlap" in L.wmc_last_error().decode()
+    assert L.wmc3_backward(None, None, None, 5, 0.0, P(1 << 23), 2, P(1 << 20), None, P(1 << 21),
+                           None, P(1 << 24), need, s, None) == wmc.WMC_EINVAL
+    assert L.wmc3_backward(P(4096), None, None, 5, 0.0, P(1 << 23), 2, P(1 << 20), P(1 << 21),
+                           None, None, P(1 << 24), need, s, None) == wmc.WMC_EINVAL
+
+
 def test_valid_call_without_device_reports_hip_error(wmc):
     """A valid call on a machine without a gfx950 device fails cleanly (no
     crash), with a HIP or unsupported-device status."""
