@@ -401,78 +401,157 @@ struct Gather3Args {
     float dt;
     int32_t data;
     int64_t n, d, h, w, ld, ss, vs;
+    int32_t R, nstrip, nseg;
 };
 
-__device__ __forceinline__ int clamp3(int v, int n) { return v < 0 ? 0 : (v < n ? v : n - 1); }
-
-// One block per image row (volume, z, y) at a time, the threads along x.
+// One wave per work item -- 64 columns of one row y of one volume (a lane
+// per column, no halo) and a segment [z0, z1) of voxel planes -- streaming
+// along z.  Each plane p of the walk (z0 - 1 .. z1, inside the volume) is
+// loaded once as the 3x3 patch of (selection, cotangent) around the lane's
+// column and feeds the three voxel planes it borders:
+//   acc(v) = sum over sources s and taps o with clamp(s + o) = v of
+//            w_{m(s)}[o] g(s).
+// Along z the ring planes -1 and D are folded by adding their contributions
+// to voxel planes 0 and D-1.  Along y and x the source in the voxel's own
+// row (column) also contributes the taps of the ring rows (columns) that
+// clamp onto it: o_y in {0, -1 if y = 0, +1 if y = H-1}, likewise o_x.
+// Integer weights from a table of the 18 kernels in LDS; fixed summation
+// order (deterministic).
 __global__ __launch_bounds__(256) void k_adjgather3d(Gather3Args A) {
-    __shared__ int tab[18 * 27];  // tab[i * 27 + (oz+1)*9 + (oy+1)*3 + (ox+1)]
+    // tab: the 18 kernels, tab[i * 27 + (oz+1)*9 + (oy+1)*3 + (ox+1)].
+    // tabx[c]: the same with the x ring folded onto the own column for the
+    // lane's case c (bit 0: x = 0, the ring column -1; bit 1: x = W-1, the
+    // ring column W): entry (oz, oy, 0) += (oz, oy, -1) [bit 0] + (oz, oy, +1)
+    // [bit 1].
+    __shared__ int tab[18 * 27];
+    __shared__ int tabx[4][18 * 27];
     for (int t = threadIdx.x; t < 18 * 27; t += 256) {
         const int o = t % 27;
         tab[t] = tap3(t / 27, o / 9 - 1, (o / 3) % 3 - 1, o % 3 - 1);
     }
     __syncthreads();
+    for (int t = threadIdx.x; t < 4 * 18 * 27; t += 256) {
+        const int c = t / (18 * 27), e = t % (18 * 27);
+        int w = tab[e];
+        if (e % 3 == 1) {  // ox = 0
+            if (c & 1) w += tab[e - 1];
+            if (c & 2) w += tab[e + 1];
+        }
+        tabx[c][e] = w;
+    }
+    __syncthreads();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t per_vol = (int64_t)A.nseg * A.h * A.nstrip;
+    const int64_t total = A.n * per_vol;
+    const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
+    if (item >= total) return;
     const int D = (int)A.d, H = (int)A.h, W = (int)A.w;
-    const int64_t rows = A.n * A.d * A.h;
-    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
-        const int y = (int)(r % H);
-        const int64_t zv = r / H;
-        const int z = (int)(zv % D);
-        const int v = (int)(zv / D);
-        const int64_t base = (int64_t)v * A.vs;
-        const bool data = A.data != 0;
-        const float lam = data ? A.lam[v] : 0.0f;
-        const Coef cf = make_coef(lam, A.dt, data);
-        const float keep = data ? 1.0f - cf.delta : 1.0f;
-        const float coef = data ? cf.delta * (lam / 56.0f) : cf.delta / 56.0f;
-        const bool zyin = z > 0 && z < D - 1 && y > 0 && y < H - 1;
-        for (int x = threadIdx.x; x < W; x += 256) {
-            float acc = 0.0f;
-            if (zyin && x > 0 && x < W - 1) {
-                // interior: the one tap o = -(dz, dy, dx) of each neighbour
+    const int v = (int)(item / per_vol);
+    int64_t rem = item - (int64_t)v * per_vol;
+    const int seg = (int)(rem / ((int64_t)H * A.nstrip));
+    rem -= (int64_t)seg * H * A.nstrip;
+    const int y = (int)(rem / A.nstrip);
+    const int strip = (int)(rem - (int64_t)y * A.nstrip);
+    const int x = strip * 64 + lane;
+    const bool own = x < W;
+    const int z0 = seg * A.R;
+    const int z1 = z0 + A.R < D ? z0 + A.R : D;
+    const int64_t base = (int64_t)v * A.vs;
+    const bool data = A.data != 0;
+    const float lam = data ? A.lam[v] : 0.0f;
+    const Coef cf = make_coef(lam, A.dt, data);
+    const float keep = data ? 1.0f - cf.delta : 1.0f;
+    const float coef = data ? cf.delta * (lam / 56.0f) : cf.delta / 56.0f;
+
+    // columns x-1, x, x+1 (clamped for the loads) and their validity
+    int xs[3];
+    bool xv[3];
 #pragma unroll
-                for (int dz = -1; dz <= 1; ++dz)
+    for (int i = 0; i < 3; ++i) {
+        const int xx = x + i - 1;
+        xv[i] = xx >= 0 && xx < W;
+        xs[i] = xx < 0 ? 0 : (xx < W ? xx : W - 1);
+    }
+    bool yv[3];
+    int64_t yo[3];
 #pragma unroll
-                    for (int dy = -1; dy <= 1; ++dy)
+    for (int i = 0; i < 3; ++i) {
+        const int yy = y + i - 1;
+        yv[i] = yy >= 0 && yy < H;
+        yo[i] = (int64_t)(yy < 0 ? 0 : (yy < H ? yy : H - 1)) * A.ld;
+    }
+    // ring folds: the own column through the lane's table, the own row
+    // (rows 0 and H-1, the same for the whole wave) by extra taps
+    const bool ylo = y == 0, yhi = y == H - 1;
+    const int* tl = tabx[(x == 0 ? 1 : 0) | (x == W - 1 ? 2 : 0)];
+
+    // weight of source (dy, dx) of the patch towards target plane offset oz:
+    // the sum of its taps over the clamp preimage of the lane's voxel
+    auto weight = [&](int m, int oz, int dy, int dx) {
+        const int* t = tl + m * 27 + (oz + 1) * 9 + (1 - dx);
+        int w = t[(1 - dy) * 3];
+        if (dy == 0) {
+            if (ylo) w += t[0];  // oy = -1
+            if (yhi) w += t[6];  // oy = +1
+        }
+        return w;
+    };
+
+    float acc_m = 0.0f, acc_c = 0.0f, acc_n = 0.0f;  // voxel planes p-1, p, p+1
+    float g_c = 0.0f;  // own cotangent of the previous plane (p-1 while plane p is added)
+    const int ps = z0 - 1 > 0 ? z0 - 1 : 0;
+    const int pl = z1 < D - 1 ? z1 : D - 1;
+    for (int p = ps; p <= pl; ++p) {
+        uint8_t ms[9];
+        float gs[9];
+        const int64_t pb = base + (int64_t)p * A.ss;
 #pragma unroll
-                        for (int dx = -1; dx <= 1; ++dx) {
-                            const int64_t q = base + (int64_t)(z + dz) * A.ss + (int64_t)(y + dy) * A.ld + x + dx;
-                            const int wgt = tab[A.sel[q] * 27 + 13 - (dz * 9 + dy * 3 + dx)];
-                            acc = __builtin_fmaf((float)wgt, A.g[q], acc);
-                        }
-            } else {
-                // border: every tap o of a neighbour x' with clamp(x' + o) = v
-                for (int dz = -1; dz <= 1; ++dz) {
-                    const int zz = z + dz;
-                    if (zz < 0 || zz >= D) continue;
-                    for (int dy = -1; dy <= 1; ++dy) {
-                        const int yy = y + dy;
-                        if (yy < 0 || yy >= H) continue;
-                        for (int dx = -1; dx <= 1; ++dx) {
-                            const int xx = x + dx;
-                            if (xx < 0 || xx >= W) continue;
-                            const int64_t q = base + (int64_t)zz * A.ss + (int64_t)yy * A.ld + xx;
-                            const int* tw = tab + A.sel[q] * 27;
-                            int wsum = 0;
-                            for (int oz = -1; oz <= 1; ++oz) {
-                                if (clamp3(zz + oz, D) != z) continue;
-                                for (int oy = -1; oy <= 1; ++oy) {
-                                    if (clamp3(yy + oy, H) != y) continue;
-                                    for (int ox = -1; ox <= 1; ++ox)
-                                        if (clamp3(xx + ox, W) == x) wsum += tw[(oz + 1) * 9 + (oy + 1) * 3 + ox + 1];
-                                }
-                            }
-                            acc = __builtin_fmaf((float)wsum, A.g[q], acc);
-                        }
-                    }
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                ms[i * 3 + j] = A.sel[pb + yo[i] + xs[j]];
+                gs[i * 3 + j] = A.g[pb + yo[i] + xs[j]];
+            }
+        float t[3] = {0.0f, 0.0f, 0.0f};  // towards planes p-1, p, p+1
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const bool ok = yv[i] && xv[j];
+                const int m = ms[i * 3 + j];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    // source plane p, target plane p + k - 1: tap o_z = k - 1
+                    const int w = ok ? weight(m, k - 1, i - 1, j - 1) : 0;
+                    t[k] = __builtin_fmaf((float)w, gs[i * 3 + j], t[k]);
                 }
             }
-            const int64_t o = base + (int64_t)z * A.ss + (int64_t)y * A.ld + x;
-            const float gp = __builtin_fmaf(coef, acc, keep * A.g[o]);
+        // ring planes -1 and D fold onto planes 0 and D-1
+        acc_m += p > 0 ? t[0] : 0.0f;
+        acc_c += t[1];
+        if (p == 0) acc_c += t[0];
+        if (p == D - 1) acc_c += t[2];
+        acc_n += p < D - 1 ? t[2] : 0.0f;
+        // voxel plane p-1 is complete
+        const int zf = p - 1;
+        if (zf >= z0 && zf < z1 && own) {
+            const int64_t o = base + (int64_t)zf * A.ss + yo[1] + x;
+            const float gp = __builtin_fmaf(coef, acc_m, keep * g_c);
             A.g_prev[o] = gp;
             if (A.g_f) A.g_f[o] += gp;
         }
+        acc_m = acc_c;
+        acc_c = acc_n;
+        acc_n = 0.0f;
+        g_c = gs[4];
+    }
+    // the last plane of the volume completes with the walk
+    if (pl == D - 1 && pl >= z0 && pl < z1 && own) {
+        const int64_t o = base + (int64_t)pl * A.ss + yo[1] + x;
+        const float gp = __builtin_fmaf(coef, acc_m, keep * g_c);
+        A.g_prev[o] = gp;
+        if (A.g_f) A.g_f[o] += gp;
     }
 }
 
@@ -567,9 +646,11 @@ hipError_t launch_adjgather3d(const float* g, const uint8_t* sel, float* g_prev,
     a.ld = ld;
     a.ss = ss;
     a.vs = vs;
-    const int64_t rows = n * d * h;
-    const int64_t blocks = rows < ((int64_t)1 << 20) ? rows : ((int64_t)1 << 20);
-    hipLaunchKernelGGL(k_adjgather3d, dim3((unsigned)blocks), dim3(256), 0, st, a);
+    a.nstrip = (int)((w + 63) / 64);
+    a.R = vol_rows(n, d, h, a.nstrip);
+    a.nseg = (int)((d + a.R - 1) / a.R);
+    const int64_t total = n * (int64_t)a.nseg * h * a.nstrip;
+    hipLaunchKernelGGL(k_adjgather3d, dim3((unsigned)((total + 3) / 4)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
