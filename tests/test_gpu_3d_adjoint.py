@@ -277,3 +277,39 @@ def test_full_volume_one_step_64cubed(wmc):
     scale = dudlam_scale(U.astype(np.float64), f.astype(np.float64), lam, 0.5, m,
                          g.astype(np.float64))
     assert abs(float(g_lam[0]) - glam) <= 1e-5 * scale + 1e-6
+
+
+def test_adjoint_volume_beyond_2_pow_31_elements(wmc):
+    """A 1300^3 volume (2.2e9 voxels, 64-bit offsets in both adjoint
+    kernels): one step's dL/dU^0 and dL/df at sampled voxels, corners
+    included, against the oracle on 7^3 crops with the GPU's selections
+    (a voxel's gradient depends only on the selections and cotangents of
+    its 27 neighbours, all inside the crop; where the crop is cut by the
+    volume's border, that border is the real one)."""
+    n = 1300
+    gen = torch.Generator(device="cuda:0").manual_seed(5)
+    f = torch.rand((n, n, n), device="cuda:0", generator=gen)
+    g = torch.rand((n, n, n), device="cuda:0", generator=gen) - 0.5
+    out, ck = wmc.solve3(f, 1.0, 1, ckpt_every=1)
+    del out
+    g_f, g_u0, _ = wmc.backward3(g, f, 1.0, 1, ck, 1)
+    del ck
+    out, am = wmc.step3(f, f, 1.0, return_argmin=True)
+    del out
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(6)
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (n - 1, 0, n - 1), (0, n - 1, 0), (650, 0, 1299)]
+    pts += [tuple(int(c) for c in rng.integers(0, n, 3)) for _ in range(12)]
+    for (z, y, x) in pts:
+        lo = [max(0, c - 3) for c in (z, y, x)]
+        hi = [min(n, c + 4) for c in (z, y, x)]
+        sl = tuple(slice(a, b) for a, b in zip(lo, hi))
+        fc = f[sl].cpu().numpy().astype(np.float64)
+        gc = g[sl].cpu().numpy().astype(np.float64)
+        mc = am[sl].cpu().numpy().astype(np.int8)
+        gU, gfd, _ = oracle.step3_adjoint(fc, gc, fc, 1.0, m_forced=mc)
+        k = (z - lo[0], y - lo[1], x - lo[2])
+        assert abs(float(g_u0[0, z, y, x]) - gU[k]) <= 2e-5, (z, y, x)
+        assert abs(float(g_f[0, z, y, x]) - (gfd[k] + gU[k])) <= 2e-5, (z, y, x)
+    del f, g, g_f, g_u0, am
+    torch.cuda.empty_cache()
