@@ -313,3 +313,19 @@ def test_adjoint_volume_beyond_2_pow_31_elements(wmc):
         assert abs(float(g_f[0, z, y, x]) - (gfd[k] + gU[k])) <= 2e-5, (z, y, x)
     del f, g, g_f, g_u0, am
     torch.cuda.empty_cache()
+
+
+def test_binding_rejects_mismatched_shapes(wmc):
+    """The 3-D binding checks shapes before any kernel is enqueued: a
+    checkpoint buffer of another period, a cotangent or data term of
+    another shape."""
+    f = to_gpu(np.zeros((3, 4, 5)))
+    _, ck = wmc.solve3(f, 1.0, 6, ckpt_every=3)  # 2 checkpoint sets
+    with pytest.raises(ValueError, match="ckpt"):
+        wmc.backward3(f, f, 1.0, 6, ck, 2)       # period 2 needs 3 sets
+    with pytest.raises(ValueError, match="g_out"):
+        wmc.backward3(to_gpu(np.zeros((3, 4, 6))), f, 1.0, 6, ck, 3)
+    with pytest.raises(ValueError, match="f has shape"):
+        wmc.step3(f, to_gpu(np.zeros((2, 4, 5))))
+    with pytest.raises(ValueError, match="has shape"):
+        wmc.solve3(to_gpu(np.zeros((3, 4, 6))), 1.0, 2, u0=f)
