@@ -329,3 +329,25 @@ def test_binding_rejects_mismatched_shapes(wmc):
         wmc.step3(f, to_gpu(np.zeros((2, 4, 5))))
     with pytest.raises(ValueError, match="has shape"):
         wmc.solve3(to_gpu(np.zeros((3, 4, 6))), 1.0, 2, u0=f)
+
+
+@pytest.mark.parametrize("shape", [(2, 3, 4), (5, 7, 70)])
+def test_one_step_explicit_step_size(wmc, shape):
+    """Data term with an explicit dt > 0: dU'/dlam = dt H has no delta'(lam)
+    term (the default-step branch of the selection pass is off)."""
+    rng = np.random.default_rng(300 + sum(shape))
+    U = rng.uniform(0, 1, size=shape).astype(np.float32)
+    f = rng.uniform(0, 1, size=shape).astype(np.float32)
+    g = (rng.uniform(-1, 1, size=shape) + 0.5).astype(np.float32)
+    lam, dt = 2.5, 0.2
+    m = gpu_selection(wmc, U, f, lam, dt)
+    _, ck = wmc.solve3(to_gpu(f), lam, 1, dt=dt, u0=to_gpu(U), ckpt_every=1)
+    g_f, g_u0, g_lam = wmc.backward3(to_gpu(g), to_gpu(f), lam, 1, ck, 1, dt=dt, u0=to_gpu(U))
+    U64, f64, g64 = U.astype(np.float64), f.astype(np.float64), g.astype(np.float64)
+    gU, gf, glam = oracle.step3_adjoint(U64, g64, f64, lam, dt, delta_from_lam=False, m_forced=m)
+    gmax = float(np.abs(g64).max())
+    assert np.abs(g_u0[0].cpu().numpy() - gU).max() <= 2e-5 * gmax
+    assert np.allclose(g_f[0].cpu().numpy(), gf, rtol=1e-6, atol=1e-7 * gmax)
+    S = np.take_along_axis(candidates(U64), m[None].astype(np.int64), axis=0)[0]
+    scale = float(np.sum(np.abs(g64 * dt * S / 56.0)))
+    assert abs(float(g_lam[0]) - glam) <= 1e-5 * scale + 1e-7
