@@ -306,9 +306,10 @@ int wmc_fd_flow(const float* u0, float* u_out, int iters, float dt, float eps, v
  *                 wmc3_set_stride(s) floats apart, receiving U^{j ckpt_every}
  *                 (the restart points of wmc3_backward); ckpt must not
  *                 overlap u_out, ws or the inputs.
- * Single sweeps per launch (no temporal blocking: at about 120 lane
- * operations per voxel the sweep is bound by the vector ALUs, not by the
- * bytes a fused launch would save); the same errors as the 2-D entry points.
+ * Single sweeps per launch (no temporal blocking: the sweep issues its
+ * vector instructions at nearly the full rate, so it is bound by the ALUs,
+ * not by the bytes a fused launch would save); the same errors as the 2-D
+ * entry points.
  * ------------------------------------------------------------------------- */
 typedef struct {
     int64_t n, d, h, w, ld, ss, vs;

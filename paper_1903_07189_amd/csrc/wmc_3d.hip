@@ -16,11 +16,12 @@
 //   D_j = sum_o sign(n_j . o) c[o] U(x + o)       (odd part of plane j)
 // since the two sides of a plane add up to 2K.  H = S_m / 56.
 //
-// Kernel: one wave per work item -- a strip of 62 owned x-columns (one halo
-// lane each side, clamped loads: the replicate border), one y row, a
-// segment of R z-planes -- streaming along z.  At each step the wave loads
-// rows y-1, y, y+1 of the next plane, forms per-plane sums over the 3x3
-// (y, x) patch with DPP neighbours, and adds them into the pending
+// Kernel: one wave per work item -- a strip of 64 x-columns (a lane each,
+// clamped loads: the replicate border), one y row, a segment of R z-planes
+// -- streaming along z.  At each step the wave loads rows y-1, y, y+1 of
+// the next plane (and, for lanes 0 and 63, the columns just outside the
+// strip), forms per-plane sums over the 3x3 (y, x) patch with DPP
+// neighbours, and adds them into the pending
 // accumulators of the three voxels whose window contains that plane (as
 // their dz = +1, 0, -1 plane).  The voxel whose window is complete is then
 // finalised: candidates, selection, update, store.
@@ -31,8 +32,9 @@
 
 namespace wmc {
 
-constexpr int k3Halo = 1;
-constexpr int k3Step = 64 - 2 * k3Halo;
+// Strips of 64 columns, one per lane, no halo lanes: lanes 0 and 63 take
+// their outer x neighbour from a separate load of the adjacent columns.
+constexpr int k3Step = 64;
 
 // Per-plane sums of one (x, y) column over the plane's 3x3 patch, weights
 // s[dy] s[dx]: the full sum, the odd parts along x, y and the two xy
@@ -52,13 +54,16 @@ __device__ __forceinline__ void acc_zero(Acc& a) {
 }
 
 // rows t (y-1), m (y), b (y+1) of one plane: the lane's value and its x
-// neighbours from the adjacent lanes.
-__device__ __forceinline__ PlaneSums plane_sums(float t, float m, float b) {
-    float l[3], r[3], v[3] = {t, m, b};
+// neighbours from the adjacent lanes; h (rows ht, hm, hb) holds, in lane 0,
+// the column left of the strip and, in lane 63, the column right of it
+// (clamped: the replicate border).
+__device__ __forceinline__ PlaneSums plane_sums(float t, float m, float b, float ht, float hm,
+                                                float hb) {
+    float l[3], r[3], v[3] = {t, m, b}, h[3] = {ht, hm, hb};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        l[i] = from_lower_lane(v[i], v[i]);
-        r[i] = from_upper_lane(v[i], v[i]);
+        l[i] = from_lower_lane(h[i], v[i]);
+        r[i] = from_upper_lane(h[i], v[i]);
     }
     float a[3], s[3], q[3];
 #pragma unroll
@@ -184,12 +189,14 @@ struct Phase3 {
 };
 
 // One work item of the z-streaming kernels: volume v, row y, the lane's
-// column x (owned or a halo lane), clamped column and row offsets, and the
-// segment [z0, z1) of voxel planes.
+// column x (owned when inside the volume), the clamped column xc, the
+// column xh of the outer neighbour (lane 0: left of the strip, lane 63:
+// right of it, clamped; others: xc), row offsets, and the segment [z0, z1)
+// of voxel planes.
 struct Item3 {
     int v, y, x, z0, z1;
     bool own;
-    uint32_t xc;
+    uint32_t xc, xh;
     int64_t voff, ym, y0, yp;
 };
 
@@ -203,10 +210,12 @@ __device__ __forceinline__ Item3 item3(int64_t item, int64_t per_vol, int nseg, 
     rem -= (int64_t)seg * H * nstrip;
     it.y = (int)(rem / nstrip);
     const int strip = (int)(rem - (int64_t)it.y * nstrip);
-    it.x = strip * k3Step - k3Halo + lane;
-    const int ox1 = strip * k3Step + k3Step < W ? strip * k3Step + k3Step : W;
-    it.own = it.x >= strip * k3Step && it.x < ox1;
-    it.xc = (uint32_t)(it.x < 0 ? 0 : (it.x < W ? it.x : W - 1));
+    const int x0 = strip * k3Step;
+    it.x = x0 + lane;
+    it.own = it.x < W;
+    it.xc = (uint32_t)(it.x < W ? it.x : W - 1);
+    const int xo = lane == 0 ? x0 - 1 : (lane == 63 ? x0 + 64 : it.x);
+    it.xh = (uint32_t)(xo < 0 ? 0 : (xo < W ? xo : W - 1));
     it.z0 = seg * R;
     it.z1 = it.z0 + R < D ? it.z0 + R : D;
     it.voff = (int64_t)it.v * vs;
@@ -225,7 +234,7 @@ template <class Fin>
 __device__ __forceinline__ void walk3(const float* u, const float* f, const Item3& it, int D,
                                       int64_t ss, Fin&& fin) {
     struct Rows {
-        float t, m, b, f;
+        float t, m, b, f, ht, hm, hb;
     };
     auto fetch = [&](int p) {
         Rows r;
@@ -234,6 +243,9 @@ __device__ __forceinline__ void walk3(const float* u, const float* f, const Item
         r.t = ld_at<float>(pl + it.ym, it.xc);
         r.m = ld_at<float>(pl + it.y0, it.xc);
         r.b = ld_at<float>(pl + it.yp, it.xc);
+        r.ht = ld_at<float>(pl + it.ym, it.xh);
+        r.hm = ld_at<float>(pl + it.y0, it.xh);
+        r.hb = ld_at<float>(pl + it.yp, it.xh);
         r.f = (f && p >= it.z0 && p < it.z1) ? ld_at<float>(f + (int64_t)pc * ss + it.y0, it.xc) : 0.0f;
         return r;
     };
@@ -254,7 +266,7 @@ __device__ __forceinline__ void walk3(const float* u, const float* f, const Item
         const Rows r = pre[0];
         pre[0] = pre[1];
         pre[1] = fetch(p + 2);
-        const PlaneSums ps = plane_sums(r.t, r.m, r.b);
+        const PlaneSums ps = plane_sums(r.t, r.m, r.b, r.ht, r.hm, r.hb);
         add_up(acc[QM], ps);
         add_mid(acc[Q], ps);
         acc[Q].f = r.f;

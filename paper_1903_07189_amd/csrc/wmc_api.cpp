@@ -1706,7 +1706,7 @@ int check_shape3(const wmc_shape3& s) {
     if (s.n > 1 && s.vs < (s.d - 1) * s.ss + (s.h - 1) * s.ld + s.w)
         return fail(WMC_EINVAL, "shape3: vs must be >= (d-1)*ss + (h-1)*ld + w when n > 1");
     if (s.ss < 0 || s.vs < 0) return fail(WMC_EINVAL, "shape3: strides must be >= 0");
-    if (s.n * s.h * ((s.w + 61) / 62) > (int64_t)1 << 31)
+    if (s.n * s.h * ((s.w + 63) / 64) > (int64_t)1 << 31)
         return fail(WMC_EINVAL, "shape3: too many rows for one launch");
     return WMC_OK;
 }
