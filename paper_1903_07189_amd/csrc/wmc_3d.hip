@@ -431,139 +431,151 @@ struct Gather3Args {
 // order (deterministic).
 __global__ __launch_bounds__(256) void k_adjgather3d(Gather3Args A) {
     // tab: the 18 kernels, tab[i * 27 + (oz+1)*9 + (oy+1)*3 + (ox+1)].
-    // tabx[c]: the same with the x ring folded onto the own column for the
-    // lane's case c (bit 0: x = 0, the ring column -1; bit 1: x = W-1, the
-    // ring column W): entry (oz, oy, 0) += (oz, oy, -1) [bit 0] + (oz, oy, +1)
-    // [bit 1].
+    // tabf[cy * 4 + cx]: the same with the ring folded onto the own row and
+    // column for the voxel's border case (bit 0: the low ring, bit 1: the
+    // high ring; cy for rows, cx for columns): entry (oz, oy, 0) adds the
+    // taps (oz, oy, -1) [cx bit 0] and (oz, oy, +1) [cx bit 1], then entry
+    // (oz, 0, ox) adds the x-folded (oz, -1, ox) [cy bit 0] and (oz, +1, ox)
+    // [cy bit 1].  A weight is then one table read, with no branches.
     __shared__ int tab[18 * 27];
-    __shared__ int tabx[4][18 * 27];
+    __shared__ int tabf[16][18 * 27];
     for (int t = threadIdx.x; t < 18 * 27; t += 256) {
         const int o = t % 27;
         tab[t] = tap3(t / 27, o / 9 - 1, (o / 3) % 3 - 1, o % 3 - 1);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < 4 * 18 * 27; t += 256) {
-        const int c = t / (18 * 27), e = t % (18 * 27);
+    auto xfold = [&](int cx, int e) {  // x-folded entry e for case cx
         int w = tab[e];
         if (e % 3 == 1) {  // ox = 0
-            if (c & 1) w += tab[e - 1];
-            if (c & 2) w += tab[e + 1];
+            if (cx & 1) w += tab[e - 1];
+            if (cx & 2) w += tab[e + 1];
         }
-        tabx[c][e] = w;
+        return w;
+    };
+    for (int t = threadIdx.x; t < 16 * 18 * 27; t += 256) {
+        const int c = t / (18 * 27), e = t % (18 * 27);
+        const int cy = c >> 2, cx = c & 3;
+        int w = xfold(cx, e);
+        if ((e / 3) % 3 == 1) {  // oy = 0
+            if (cy & 1) w += xfold(cx, e - 3);
+            if (cy & 2) w += xfold(cx, e + 3);
+        }
+        tabf[c][e] = w;
     }
     __syncthreads();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int64_t per_vol = (int64_t)A.nseg * A.h * A.nstrip;
     const int64_t total = A.n * per_vol;
-    const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
-    if (item >= total) return;
     const int D = (int)A.d, H = (int)A.h, W = (int)A.w;
-    const int v = (int)(item / per_vol);
-    int64_t rem = item - (int64_t)v * per_vol;
-    const int seg = (int)(rem / ((int64_t)H * A.nstrip));
-    rem -= (int64_t)seg * H * A.nstrip;
-    const int y = (int)(rem / A.nstrip);
-    const int strip = (int)(rem - (int64_t)y * A.nstrip);
-    const int x = strip * 64 + lane;
-    const bool own = x < W;
-    const int z0 = seg * A.R;
-    const int z1 = z0 + A.R < D ? z0 + A.R : D;
-    const int64_t base = (int64_t)v * A.vs;
-    const bool data = A.data != 0;
-    const float lam = data ? A.lam[v] : 0.0f;
-    const Coef cf = make_coef(lam, A.dt, data);
-    const float keep = data ? 1.0f - cf.delta : 1.0f;
-    const float coef = data ? cf.delta * (lam / 56.0f) : cf.delta / 56.0f;
+    // persistent blocks (the tables are built once per block): in round r,
+    // block b takes the group of 4 items xcd_remap(b) + r * gridDim.x
+    for (int64_t grp = xcd_remap(blockIdx.x, gridDim.x); grp * 4 < total; grp += gridDim.x) {
+        const int64_t item = grp * 4 + wv;
+        if (item >= total) break;
+        const int v = (int)(item / per_vol);
+        int64_t rem = item - (int64_t)v * per_vol;
+        const int seg = (int)(rem / ((int64_t)H * A.nstrip));
+        rem -= (int64_t)seg * H * A.nstrip;
+        const int y = (int)(rem / A.nstrip);
+        const int strip = (int)(rem - (int64_t)y * A.nstrip);
+        const int x = strip * 64 + lane;
+        const bool own = x < W;
+        const int z0 = seg * A.R;
+        const int z1 = z0 + A.R < D ? z0 + A.R : D;
+        const int64_t base = (int64_t)v * A.vs;
+        const bool data = A.data != 0;
+        const float lam = data ? A.lam[v] : 0.0f;
+        const Coef cf = make_coef(lam, A.dt, data);
+        const float keep = data ? 1.0f - cf.delta : 1.0f;
+        const float coef = data ? cf.delta * (lam / 56.0f) : cf.delta / 56.0f;
 
-    // columns x-1, x, x+1 (clamped for the loads) and their validity
-    int xs[3];
-    bool xv[3];
+        // columns x-1, x, x+1 (clamped for the loads) and their validity
+        int xs[3];
+        bool xv[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const int xx = x + i - 1;
-        xv[i] = xx >= 0 && xx < W;
-        xs[i] = xx < 0 ? 0 : (xx < W ? xx : W - 1);
-    }
-    bool yv[3];
-    int64_t yo[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const int yy = y + i - 1;
-        yv[i] = yy >= 0 && yy < H;
-        yo[i] = (int64_t)(yy < 0 ? 0 : (yy < H ? yy : H - 1)) * A.ld;
-    }
-    // ring folds: the own column through the lane's table, the own row
-    // (rows 0 and H-1, the same for the whole wave) by extra taps
-    const bool ylo = y == 0, yhi = y == H - 1;
-    const int* tl = tabx[(x == 0 ? 1 : 0) | (x == W - 1 ? 2 : 0)];
-
-    // weight of source (dy, dx) of the patch towards target plane offset oz:
-    // the sum of its taps over the clamp preimage of the lane's voxel
-    auto weight = [&](int m, int oz, int dy, int dx) {
-        const int* t = tl + m * 27 + (oz + 1) * 9 + (1 - dx);
-        int w = t[(1 - dy) * 3];
-        if (dy == 0) {
-            if (ylo) w += t[0];  // oy = -1
-            if (yhi) w += t[6];  // oy = +1
+        for (int i = 0; i < 3; ++i) {
+            const int xx = x + i - 1;
+            xv[i] = xx >= 0 && xx < W;
+            xs[i] = xx < 0 ? 0 : (xx < W ? xx : W - 1);
         }
-        return w;
-    };
+        bool yv[3];
+        int64_t yo[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int yy = y + i - 1;
+            yv[i] = yy >= 0 && yy < H;
+            yo[i] = (int64_t)(yy < 0 ? 0 : (yy < H ? yy : H - 1)) * A.ld;
+        }
+        // the voxel column's border case selects its prefolded table
+        const int* tl = tabf[((y == 0 ? 1 : 0) | (y == H - 1 ? 2 : 0)) * 4 +
+                             ((x == 0 ? 1 : 0) | (x == W - 1 ? 2 : 0))];
 
-    float acc_m = 0.0f, acc_c = 0.0f, acc_n = 0.0f;  // voxel planes p-1, p, p+1
-    float g_c = 0.0f;  // own cotangent of the previous plane (p-1 while plane p is added)
-    const int ps = z0 - 1 > 0 ? z0 - 1 : 0;
-    const int pl = z1 < D - 1 ? z1 : D - 1;
-    for (int p = ps; p <= pl; ++p) {
-        uint8_t ms[9];
-        float gs[9];
-        const int64_t pb = base + (int64_t)p * A.ss;
+        float acc_m = 0.0f, acc_c = 0.0f, acc_n = 0.0f;  // voxel planes p-1, p, p+1
+        float g_c = 0.0f;  // own cotangent of the previous plane (p-1 while plane p is added)
+        const int ps = z0 - 1 > 0 ? z0 - 1 : 0;
+        const int pl = z1 < D - 1 ? z1 : D - 1;
+        for (int p = ps; p <= pl; ++p) {
+            uint8_t ms[9];
+            float gs[9];
+            const int64_t pb = base + (int64_t)p * A.ss;
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                ms[i * 3 + j] = A.sel[pb + yo[i] + xs[j]];
-                gs[i * 3 + j] = A.g[pb + yo[i] + xs[j]];
-            }
-        float t[3] = {0.0f, 0.0f, 0.0f};  // towards planes p-1, p, p+1
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const bool ok = yv[i] && xv[j];
-                const int m = ms[i * 3 + j];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    // source plane p, target plane p + k - 1: tap o_z = k - 1
-                    const int w = ok ? weight(m, k - 1, i - 1, j - 1) : 0;
-                    t[k] = __builtin_fmaf((float)w, gs[i * 3 + j], t[k]);
+                for (int j = 0; j < 3; ++j) {
+                    ms[i * 3 + j] = A.sel[pb + yo[i] + xs[j]];
+                    gs[i * 3 + j] = A.g[pb + yo[i] + xs[j]];
                 }
+            // weights: source (dy, dx) = (i - 1, j - 1) of plane p towards
+            // target plane p + k - 1 (tap o_z = k - 1, o_y = -dy, o_x = -dx),
+            // all 27 table reads issued before the products
+            int wt[27];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int* row = tl + ms[i * 3 + j] * 27 + (2 - i) * 3 + (2 - j);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) wt[(i * 3 + j) * 3 + k] = row[k * 9];
+                }
+            float t[3] = {0.0f, 0.0f, 0.0f};  // towards planes p-1, p, p+1
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const bool ok = yv[i] && xv[j];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const float w = ok ? (float)wt[(i * 3 + j) * 3 + k] : 0.0f;
+                        t[k] = __builtin_fmaf(w, gs[i * 3 + j], t[k]);
+                    }
+                }
+            // ring planes -1 and D fold onto planes 0 and D-1
+            acc_m += p > 0 ? t[0] : 0.0f;
+            acc_c += t[1];
+            if (p == 0) acc_c += t[0];
+            if (p == D - 1) acc_c += t[2];
+            acc_n += p < D - 1 ? t[2] : 0.0f;
+            // voxel plane p-1 is complete
+            const int zf = p - 1;
+            if (zf >= z0 && zf < z1 && own) {
+                const int64_t o = base + (int64_t)zf * A.ss + yo[1] + x;
+                const float gp = __builtin_fmaf(coef, acc_m, keep * g_c);
+                A.g_prev[o] = gp;
+                if (A.g_f) A.g_f[o] += gp;
             }
-        // ring planes -1 and D fold onto planes 0 and D-1
-        acc_m += p > 0 ? t[0] : 0.0f;
-        acc_c += t[1];
-        if (p == 0) acc_c += t[0];
-        if (p == D - 1) acc_c += t[2];
-        acc_n += p < D - 1 ? t[2] : 0.0f;
-        // voxel plane p-1 is complete
-        const int zf = p - 1;
-        if (zf >= z0 && zf < z1 && own) {
-            const int64_t o = base + (int64_t)zf * A.ss + yo[1] + x;
+            acc_m = acc_c;
+            acc_c = acc_n;
+            acc_n = 0.0f;
+            g_c = gs[4];
+        }
+        // the last plane of the volume completes with the walk
+        if (pl == D - 1 && pl >= z0 && pl < z1 && own) {
+            const int64_t o = base + (int64_t)pl * A.ss + yo[1] + x;
             const float gp = __builtin_fmaf(coef, acc_m, keep * g_c);
             A.g_prev[o] = gp;
             if (A.g_f) A.g_f[o] += gp;
         }
-        acc_m = acc_c;
-        acc_c = acc_n;
-        acc_n = 0.0f;
-        g_c = gs[4];
-    }
-    // the last plane of the volume completes with the walk
-    if (pl == D - 1 && pl >= z0 && pl < z1 && own) {
-        const int64_t o = base + (int64_t)pl * A.ss + yo[1] + x;
-        const float gp = __builtin_fmaf(coef, acc_m, keep * g_c);
-        A.g_prev[o] = gp;
-        if (A.g_f) A.g_f[o] += gp;
     }
 }
 
@@ -662,7 +674,13 @@ hipError_t launch_adjgather3d(const float* g, const uint8_t* sel, float* g_prev,
     a.R = vol_rows(n, d, h, a.nstrip);
     a.nseg = (int)((d + a.R - 1) / a.R);
     const int64_t total = n * (int64_t)a.nseg * h * a.nstrip;
-    hipLaunchKernelGGL(k_adjgather3d, dim3((unsigned)((total + 3) / 4)), dim3(256), 0, st, a);
+    // persistent: at most the resident blocks (4 per CU: 33 KB of LDS each)
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t groups = (total + 3) / 4;
+    const int64_t cap = (int64_t)4 * (cus > 0 ? cus : 256);
+    hipLaunchKernelGGL(k_adjgather3d, dim3((unsigned)(groups < cap ? groups : cap)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
