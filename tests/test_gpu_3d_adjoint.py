@@ -351,3 +351,21 @@ def test_one_step_explicit_step_size(wmc, shape):
     S = np.take_along_axis(candidates(U64), m[None].astype(np.int64), axis=0)[0]
     scale = float(np.sum(np.abs(g64 * dt * S / 56.0)))
     assert abs(float(g_lam[0]) - glam) <= 1e-5 * scale + 1e-7
+
+
+def test_zero_steps(wmc):
+    """A solve of 0 steps returns U^0: its backward gives dL/dU^0 = g_out,
+    dL/df = g_out when U^0 = f (zero when u0 is given), dL/dlam = 0."""
+    rng = np.random.default_rng(8)
+    f = to_gpu(rng.uniform(0, 1, size=(3, 5, 70)))
+    u0 = to_gpu(rng.uniform(0, 1, size=(3, 5, 70)))
+    g = to_gpu(rng.normal(size=(3, 5, 70)))
+    out, ck = wmc.solve3(f, 1.3, 0, ckpt_every=2)
+    assert torch.equal(out, f)
+    g_f, g_u0, g_lam = wmc.backward3(g, f, 1.3, 0, ck, 2)
+    assert torch.equal(g_u0[0], g) and torch.equal(g_f[0], g)
+    assert float(g_lam[0]) == 0.0
+    _, ck = wmc.solve3(f, 1.3, 0, u0=u0, ckpt_every=2)
+    g_f, g_u0, g_lam = wmc.backward3(g, f, 1.3, 0, ck, 2, u0=u0)
+    assert torch.equal(g_u0[0], g)
+    assert torch.count_nonzero(g_f) == 0 and float(g_lam[0]) == 0.0
