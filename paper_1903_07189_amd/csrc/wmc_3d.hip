@@ -200,8 +200,8 @@ struct Item3 {
     int64_t voff, ym, y0, yp;
 };
 
-__device__ __forceinline__ Item3 item3(int64_t item, int64_t per_vol, int nseg, int nstrip, int R,
-                                       int D, int H, int W, int64_t ld, int64_t vs) {
+__device__ __forceinline__ Item3 item3(int64_t item, int64_t per_vol, int nstrip, int R, int D,
+                                       int H, int W, int64_t ld, int64_t vs) {
     Item3 it;
     const int lane = threadIdx.x & 63;
     it.v = (int)(item / per_vol);
@@ -222,7 +222,6 @@ __device__ __forceinline__ Item3 item3(int64_t item, int64_t per_vol, int nseg, 
     it.ym = (int64_t)(it.y > 0 ? it.y - 1 : 0) * ld;
     it.y0 = (int64_t)it.y * ld;
     it.yp = (int64_t)(it.y + 1 < H ? it.y + 1 : H - 1) * ld;
-    (void)nseg;
     return it;
 }
 
@@ -291,7 +290,7 @@ __global__ __launch_bounds__(256) void k_stream3d(Vol3Args A) {
     const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
     if (item >= total) return;
     const int D = (int)A.d, H = (int)A.h, W = (int)A.w;
-    const Item3 it = item3(item, per_vol, A.nseg, A.nstrip, A.R, D, H, W, A.ld, A.vs);
+    const Item3 it = item3(item, per_vol, A.nstrip, A.R, D, H, W, A.ld, A.vs);
     const float* u = A.u + it.voff;
     const bool data = A.mode == kModeData;
     const float* f = data ? A.f + it.voff : nullptr;
@@ -352,7 +351,7 @@ __global__ __launch_bounds__(256) void k_adjsel3d(Adj3Args A) {
     const int64_t item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
     if (item >= total) return;
     const int D = (int)A.d, H = (int)A.h, W = (int)A.w;
-    const Item3 it = item3(item, per_vol, A.nseg, A.nstrip, A.R, D, H, W, A.ld, A.vs);
+    const Item3 it = item3(item, per_vol, A.nstrip, A.R, D, H, W, A.ld, A.vs);
     const bool data = A.f != nullptr;
     const float* u = A.u + it.voff;
     const float* f = data ? A.f + it.voff : nullptr;
