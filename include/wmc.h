@@ -30,6 +30,10 @@
  *   f and the 3x3 neighbourhood) and 1 for the pure curvature flow.
  * - Arithmetic is FP32; results are bitwise independent of the tiling,
  *   temporal-blocking depth and batching chosen by the library.
+ * - Non-finite inputs are not checked.  A NaN response never wins a strict
+ *   comparison, but the selection is evaluated as a pairwise tournament, so
+ *   near a NaN (or Inf minus Inf) input the chosen response is unspecified;
+ *   for finite inputs the tournament and the rule above are the same.
  * - The library runs on gfx950 only (WMC_EUNSUPPORTED elsewhere).
  */
 #ifndef WMC_H
