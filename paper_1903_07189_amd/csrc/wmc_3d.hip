@@ -27,6 +27,8 @@
 // finalised: candidates, selection, update, store.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "wmc_device.hpp"
 #include "wmc_internal.h"
 
@@ -581,10 +583,16 @@ __global__ __launch_bounds__(256) void k_adjgather3d(Gather3Args A) {
 // ~16K work items, 8..128 planes per item.  (Round-filling row counts, which
 // help the 2-D kernels, measured slower here: this kernel hides latency
 // better with more, shorter items.)
+// WMC_VOL_ROWS=R: planes per work item, at least the default (the adjoint's
+// workspace holds the dL/dlam partials of the default item count).
 static int vol_rows(int64_t n, int64_t d, int64_t h, int64_t strips) {
     const int64_t cols = n * h * strips;
     int R = 8;
     while (R < 128 && cols * ((d + R - 1) / R) > 16384) R *= 2;
+    if (const char* env = std::getenv("WMC_VOL_ROWS")) {
+        const int r = std::atoi(env);
+        if (r > R && r <= 4096) R = r;
+    }
     return R;
 }
 
