@@ -171,3 +171,30 @@ def test_constant_volume_gradient_is_plain_relaxation():
     assert np.array_equal(gU, 0.5 * g)
     assert np.array_equal(gf, 0.5 * g)
     assert glam == 0.0
+
+
+def test_step3_with_forced_selection_against_library_candidates():
+    """The step with a forced selection is the update through that
+    candidate: U + delta((f - U) + lam S_m / 56) with S_m from an independent
+    evaluation (scipy's correlation with replicate borders); without forcing
+    it is the one-step solve, and its recorded selection is the first
+    minimum of those candidates."""
+    from scipy import ndimage
+    rng = np.random.default_rng(17)
+    shape = (4, 5, 6)
+    U = rng.uniform(0, 1, shape)
+    f = rng.uniform(0, 1, shape)
+    lam, delta = 0.8, 0.45
+    S = np.stack([ndimage.correlate(U, k.astype(np.float64), mode="nearest")
+                  for k in oracle.kernels3()])
+    out, m = oracle.step3(U, f, lam, delta, return_argmin=True)
+    assert np.allclose(out, oracle.solve3(f, lam, 1, delta=delta, u0=U), atol=1e-15)
+    assert np.array_equal(m, np.argmin(np.abs(S), axis=0))
+    forced = rng.integers(0, 18, size=shape).astype(np.int8)
+    got, used = oracle.step3(U, f, lam, delta, m_forced=forced, return_argmin=True)
+    Sm = np.take_along_axis(S, forced[None].astype(np.int64), axis=0)[0]
+    assert np.array_equal(used, forced)
+    assert np.allclose(got, U + delta * ((f - U) + lam * Sm / 56.0), atol=1e-13)
+    # flow mode
+    got = oracle.step3(U, None, 1.0, 0.3, m_forced=forced)
+    assert np.allclose(got, U + 0.3 * Sm / 56.0, atol=1e-13)
