@@ -136,7 +136,11 @@ int wmc_solve(const float* f, const float* u0, float* u_out, const float* lam, i
 
 /* The launch shape wmc_solve(f, u0, ..., tune = NULL) uses for this shape:
  * the cached autotuner result, or a fresh search timed on ws (which it may
- * overwrite; nothing else is written).  Arguments as for wmc_solve. */
+ * overwrite; nothing else is written).  Arguments as for wmc_solve.  With
+ * ws_bytes >= 2 * wmc_solve_workspace(s) + 256 the search's launches
+ * ping-pong between two plane sets in ws, as the solve does (the timings
+ * then match the solve's more closely); with less they read U from u0 (or
+ * f). */
 int wmc_solve_tuning(const float* f, const float* u0, const float* lam, float dt, void* ws,
                      size_t ws_bytes, wmc_shape s, wmc_tuning* out, void* stream);
 

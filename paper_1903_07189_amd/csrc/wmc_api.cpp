@@ -697,12 +697,12 @@ int tune_search(Run&& run, Rows&& rows, hipStream_t st, Tuned* best_out) {
     std::vector<Cand> cands;
     Tuned best_t{2, 4, 64};
     int rc = WMC_OK;
-    // best of three timings of `launches` back-to-back launches, per sweep
-    auto time_of = [&](const Tuned& t, int launches, double* per_sweep) -> int {
+    // best of `reps` timings of `launches` back-to-back launches, per sweep
+    auto time_of = [&](const Tuned& t, int launches, int reps, double* per_sweep) -> int {
         int r = run(t.C, t.T, t.R, st);  // warm-up
         if (r) return r;
         float ms_best = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
+        for (int rep = 0; rep < reps; ++rep) {
             WMC_HIP(hipEventRecord(e0, st), "hipEventRecord");
             for (int l = 0; l < launches; ++l) {
                 r = run(t.C, t.T, t.R, st);
@@ -717,34 +717,96 @@ int tune_search(Run&& run, Rows&& rows, hipStream_t st, Tuned* best_out) {
         *per_sweep = ms_best / ((double)t.T * launches);
         return WMC_OK;
     };
-    // every candidate on single launches, then the four fastest again on
-    // runs of eight launches, which the single-launch figures rank
-    // unreliably when candidates are within a few per cent
+    // best of `reps` replays of one graph of `launches` launches, per sweep.
+    // The solve replays its launch sequence as a graph; plain launches timed
+    // some shapes up to 4% slower than the solve then ran them, others 1%.
+    // The warm-up launch on st creates whatever the candidate's plan needs,
+    // so that the capture records kernel launches only.
+    hipStream_t cs = nullptr;
+    auto time_graph = [&](const Tuned& t, int launches, int reps, double* per_sweep) -> int {
+        int r = run(t.C, t.T, t.R, st);  // warm-up
+        if (r) return r;
+        if (!cs) WMC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        WMC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        for (int l = 0; l < launches && r == WMC_OK; ++l) r = run(t.C, t.T, t.R, cs);
+        const hipError_t ce = hipStreamEndCapture(cs, &g);
+        if (r == WMC_OK && ce != hipSuccess) r = hip_fail(ce, "hipStreamEndCapture");
+        if (r == WMC_OK) {
+            const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            if (ie != hipSuccess) r = hip_fail(ie, "hipGraphInstantiate");
+        }
+        float ms_best = 1e30f;
+        for (int rep = -1; rep < reps && r == WMC_OK; ++rep) {  // rep -1: warm-up replay
+            hipError_t e = hipEventRecord(e0, st);
+            if (e == hipSuccess) e = hipGraphLaunch(ex, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) r = hip_fail(e, "timing a graph replay");
+            else if (rep >= 0) ms_best = std::min(ms_best, ms);
+        }
+        if (ex) (void)hipGraphExecDestroy(ex);
+        if (g) (void)hipGraphDestroy(g);
+        if (r) return r;
+        *per_sweep = ms_best / ((double)t.T * launches);
+        return WMC_OK;
+    };
+    // launches of T sweeps covering at least `sweeps` sweeps
+    auto launches_for = [](int T, int sweeps) { return std::max(1, (sweeps + T - 1) / T); };
+    const bool verbose = std::getenv("WMC_TUNE_VERBOSE") != nullptr;  // stage timings to stderr
+    // Two stages.  A fresh device first runs about 40 sweeps of one shape so
+    // that its clocks have risen before anything is timed.  Every candidate
+    // is then timed on single launches (best of three), and the six fastest
+    // again as graph replays of at least 64 sweeps (best of five), which
+    // decide: runs of 32 sweeps, best of three, measured noisier than either
+    // and dropped the fastest shape from the final comparison on some
+    // devices.
+    {
+        const Tuned w{2, 4, rows(2, 4).empty() ? 16 : rows(2, 4)[0]};
+        for (int l = 0; l < 10 && rc == WMC_OK; ++l) rc = run(w.C, w.T, w.R, st);
+        if (rc == WMC_OK) {
+            const hipError_t e = hipStreamSynchronize(st);
+            if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+        }
+        if (rc) goto done;
+    }
     for (int C : {1, 2, 4})
         for (int T : {1, 2, 3, 4, 6, 8})
             for (int R : rows(C, T)) {
                 double ps = 0.0;
-                rc = time_of(Tuned{C, T, R}, 1, &ps);
+                rc = time_of(Tuned{C, T, R}, 1, 3, &ps);
                 if (rc) goto done;
                 cands.push_back({ps, Tuned{C, T, R}});
             }
     std::sort(cands.begin(), cands.end(),
               [](const Cand& x, const Cand& y) { return x.per_sweep < y.per_sweep; });
+    if (verbose)
+        for (const Cand& c : cands)
+            std::fprintf(stderr, "wmc tune 1: C=%d T=%d R=%d %.4f us/sweep\n", c.t.C, c.t.T, c.t.R,
+                         c.per_sweep * 1e3);
+    if (cands.size() > 6) cands.resize(6);
     {
         double best = 1e30;
-        for (size_t i = 0; i < cands.size() && i < 4; ++i) {
+        for (const Cand& c : cands) {
             double ps = 0.0;
-            rc = time_of(cands[i].t, 8, &ps);
+            rc = time_graph(c.t, launches_for(c.t.T, 64), 5, &ps);
             if (rc) goto done;
+            if (verbose)
+                std::fprintf(stderr, "wmc tune 2: C=%d T=%d R=%d %.4f us/sweep\n", c.t.C, c.t.T,
+                             c.t.R, ps * 1e3);
             if (ps < best) {
                 best = ps;
-                best_t = cands[i].t;
+                best_t = c.t;
             }
         }
     }
 done:
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (cs) (void)hipStreamDestroy(cs);
     if (rc) return rc;
     *best_out = best_t;
     return WMC_OK;
@@ -809,13 +871,23 @@ std::string single_tune_key(int dev, const wmc_shape& s, int mode) {
     return k.str();
 }
 
+// alt (or null): a second writable plane set; the candidates then ping-pong
+// between alt and ws as the solve does (U never the same buffer as f, each
+// launch reading what the previous one wrote), instead of reading src.
 int tune_single(int dev, const wmc_shape& s, const float* src, const float* f, const float* lam,
-                float dt, float* ws, hipStream_t st, Tuned* t) {
+                float dt, float* ws, hipStream_t st, Tuned* t, float* alt = nullptr) {
     const int mode = f ? kModeData : kModeFlow;
-    const int C0 = std::min(2, vec_cols({src, f, ws}, s.ld, s.n > 1 ? s.ps : 0));
+    const int C0 = std::min(2, vec_cols({src, f, ws, alt}, s.ld, s.n > 1 ? s.ps : 0));
     const Tuned deflt{C0, 3, default_rows(s.n, s.h, s.w, C0, 3, dev, mode)};
     auto search = [&](Tuned* out) {
+        int flip = 0;
         auto run = [&](int C, int T, int R, hipStream_t ss) {
+            if (alt) {
+                float* a = (flip & 1) ? ws : alt;
+                float* b = (flip & 1) ? alt : ws;
+                ++flip;
+                return enqueue_single(s, a, f, b, lam, dt, C, T, R, ss);
+            }
             return enqueue_single(s, src, f, ws, lam, dt, C, T, R, ss);
         };
         auto rows = [&](int C, int T) { return candidate_rows(s.n, s.h, s.w, C, T, dev, mode); };
@@ -1110,12 +1182,12 @@ int wmc::solve_impl(const float* f, const float* u0, float* u_out, const float* 
                             &t, &graph);
     } else {
         Tuned auto_t{};
-        // with a workspace the candidates read U from u_out (contents
-        // irrelevant to the timing) rather than from f, so that, as in the
-        // solve, U and f are different planes
+        // with a workspace the candidates ping-pong between u_out and ws
+        // (contents irrelevant to the timing) rather than reading f, so that,
+        // as in the solve, U and f are different planes
         rc = tune_single(dev, s, iters >= 2 ? u_out : src0, f, lam, dt,
                          iters >= 2 ? static_cast<float*>(ws) : u_out, st,
-                         &auto_t);
+                         &auto_t, iters >= 2 ? u_out : nullptr);
         if (rc) return rc;
         rc = resolve_tuning(tune, auto_t, &t, &graph);
     }
@@ -1298,14 +1370,23 @@ int wmc_solve_tuning(const float* f, const float* u0, const float* lam, float dt
     if (!ws || ws_bytes < wmc_solve_workspace(s))
         return fail(WMC_ENOMEM, "wmc_solve_tuning: workspace smaller than wmc_solve_workspace()");
     const int64_t ext = extent_elems(s);
-    const Range rw = range_of(ws, ext, 4);
+    // with room for two plane sets (the second at the next 256-byte offset)
+    // the candidates ping-pong between them, as the solve does; with one
+    // they read U from u0 (or f)
+    const size_t set_bytes = (size_t)set_stride_elems(s) * sizeof(float);
+    const size_t alt_off = (set_bytes + 255) / 256 * 256;
+    float* alt = ws_bytes >= alt_off + set_bytes
+                     ? reinterpret_cast<float*>(static_cast<char*>(ws) + alt_off)
+                     : nullptr;
+    const Range rw = range_of(ws, alt ? (int64_t)((alt_off + set_bytes) / 4) : ext, 4);
     if (overlaps(rw, range_of(f, ext, 4)) || overlaps(rw, range_of(u0, ext, 4)))
         return fail(WMC_EINVAL, "wmc_solve_tuning: ws overlaps an input");
     int dev;
     rc = check_device(&dev);
     if (rc) return rc;
     Tuned t{};
-    rc = tune_single(dev, s, u0 ? u0 : f, f, lam, dt, static_cast<float*>(ws), as_stream(stream), &t);
+    rc = tune_single(dev, s, u0 ? u0 : f, f, lam, dt, static_cast<float*>(ws), as_stream(stream), &t,
+                     alt);
     if (rc) return rc;
     out->cols = t.C;
     out->tsteps = t.T;

@@ -524,7 +524,9 @@ def solve_tuning(f: torch.Tensor | None, lam=1.0, dt: float = 0.0, u0: torch.Ten
     require_shape(u0, ref.shape, "u0")
     s = shape_of(ref)
     L = lib()
-    ws = torch.empty(max(1, L.wmc_solve_workspace(s) // 4), dtype=torch.float32, device=ref.device)
+    # two plane sets: the search then ping-pongs between them as the solve does
+    ws = torch.empty(max(1, (2 * L.wmc_solve_workspace(s) + 256) // 4), dtype=torch.float32,
+                     device=ref.device)
     lt = _lam_tensor(lam, ref.shape[0], ref.device) if f is not None else None
     t = Tuning()
     check(L.wmc_solve_tuning(_ptr(f), _ptr(u0), _ptr(lt), float(dt), _ptr(ws), ws.numel() * 4, s,
