@@ -121,6 +121,36 @@ def test_solve_validation(wmc):
                        P(1 << 21), 1 << 12, S, None) in (wmc.WMC_EINVAL, wmc.WMC_EHIP)
 
 
+def test_solve_tuning_workspace_validation(wmc):
+    """wmc_solve_tuning: a workspace of one plane set is accepted (the search
+    reads U from f); with room for two sets (the second at the next 256-byte
+    offset) the search ping-pongs inside it, so an input overlapping the
+    second set is rejected -- and the same input beyond a one-set workspace
+    is not."""
+    import torch
+    L = wmc.lib()
+    S = wmc.Shape(1, 64, 64, 64, 4096)
+    set_bytes = L.wmc_solve_workspace(S)
+    assert set_bytes == 4096 * 4
+    lam, ws = P(64), 1 << 24
+    t = wmc.Tuning()
+    f_in_second_set = ws + set_bytes + 4000
+    # two sets: f lies inside the second one
+    assert L.wmc_solve_tuning(P(f_in_second_set), None, lam, 0.0, P(ws), 2 * set_bytes + 256, S,
+                              ctypes.byref(t), None) == wmc.WMC_EINVAL
+    assert "overlaps" in L.wmc_last_error().decode()
+    # too small for one set
+    assert L.wmc_solve_tuning(P(1 << 20), None, lam, 0.0, P(ws), set_bytes - 4, S,
+                              ctypes.byref(t), None) == wmc.WMC_ENOMEM
+    if torch.cuda.is_available():
+        return
+    # one set: the same f is outside it, so validation passes and the call
+    # stops at the missing device
+    rc = L.wmc_solve_tuning(P(f_in_second_set), None, lam, 0.0, P(ws), set_bytes, S,
+                            ctypes.byref(t), None)
+    assert rc in (wmc.WMC_EHIP, wmc.WMC_EUNSUPPORTED)
+
+
 def test_batched_validation(wmc):
     L = wmc.lib()
     imgs = (wmc.Image * 2)()

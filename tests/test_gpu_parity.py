@@ -334,6 +334,39 @@ def test_default_tuning_path(wmc, monkeypatch, tmp_path):
     assert (tmp_path / "tune.json").exists()
 
 
+@pytest.mark.parametrize("two_sets", [False, True])
+def test_tuning_search_workspaces(wmc, monkeypatch, tmp_path, two_sets):
+    """A forced search through wmc_solve_tuning, with a workspace of one
+    plane set (candidates read U from u0) or of two (candidates ping-pong in
+    the workspace), writes nothing but the workspace and returns a shape
+    whose solve is bitwise the fixed-shape one."""
+    import ctypes
+    from paper_1903_07189_amd import wmc as M
+    monkeypatch.setenv("WMC_TUNE", "force")
+    monkeypatch.setenv("WMC_TUNE_CACHE", str(tmp_path / "tune.json"))
+    rng = np.random.default_rng(16)
+    f = to_gpu(rng.uniform(0, 1, size=(2, 100, 300)))
+    u0 = to_gpu(rng.uniform(0, 1, size=(2, 100, 300)))
+    f_keep, u0_keep = f.clone(), u0.clone()
+    lam = torch.tensor([0.7, 1.5], device="cuda:0")
+    s = M.shape_of(f)
+    L = M.lib()
+    set_bytes = L.wmc_solve_workspace(s)
+    nbytes = 2 * set_bytes + 256 if two_sets else set_bytes
+    ws = torch.empty((nbytes + 3) // 4, dtype=torch.float32, device="cuda:0")
+    t = M.Tuning()
+    M.check(L.wmc_solve_tuning(M._ptr(f), M._ptr(u0), M._ptr(lam), 0.0, M._ptr(ws), nbytes,
+                               s, ctypes.byref(t), M._stream()))
+    torch.cuda.synchronize()
+    assert torch.equal(f, f_keep) and torch.equal(u0, u0_keep)
+    assert t.cols in (1, 2, 4) and t.tsteps in (1, 2, 3, 4, 6, 8) and t.seg_rows >= 1
+    got = wmc.solve(f, lam, 11, u0=u0, tuning={"cols": t.cols, "tsteps": t.tsteps,
+                                                 "seg_rows": t.seg_rows, "use_graph": 1})
+    ref = wmc.solve(f, lam, 11, u0=u0, tuning={"cols": 1, "tsteps": 1, "seg_rows": 64,
+                                                 "use_graph": 0})
+    assert torch.equal(got, ref)
+
+
 def _shadow(wmc, f32, lam, iters, mcf=False, delta=None):
     """Shadow protocol: the GPU runs `iters` steps recording its selection maps;
     the oracle follows in FP64, adopting the GPU's choice wherever it is one of
