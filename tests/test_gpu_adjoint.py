@@ -207,6 +207,28 @@ def test_autograd_function(wmc):
     assert ls.grad.shape == ()
 
 
+def test_autograd_gradients_independent_of_forward_shape(wmc):
+    """The differentiable solve's gradients are bitwise the same whatever
+    launch shape the forward uses (its states are those of single steps) and
+    whatever the checkpoint period (deterministic reductions)."""
+    rng = np.random.default_rng(14)
+    f0 = to_gpu(rng.uniform(0, 1, size=(2, 64, 136)))
+    target = to_gpu(rng.uniform(0, 1, size=(2, 64, 136)))
+    ref = None
+    for tn in [None, {"cols": 2, "tsteps": 4, "seg_rows": 16}, {"cols": 2, "tsteps": 2, "seg_rows": 8},
+               {"cols": 4, "tsteps": 3, "seg_rows": 12}, {"cols": 1, "tsteps": 1, "seg_rows": 5}]:
+        for c in (1, 3):
+            f = f0.clone().requires_grad_(True)
+            lam = torch.tensor([0.6, 1.8], device="cuda:0", requires_grad=True)
+            out = wmc.WMCSolve.apply(f, lam, 9, 0.0, c, tn)
+            ((out - target) ** 2).mean().backward()
+            got = (out.detach(), f.grad, lam.grad)
+            if ref is None:
+                ref = got
+            for a, b in zip(got, ref):
+                assert torch.equal(a, b), (tn, c)
+
+
 def test_c4_batch_against_oracle(wmc):
     """The full differentiable-layer batch (16x1x512x512, K = 20, checkpoints
     every 5): every image checked against the shadowed FP64 adjoint."""
