@@ -717,11 +717,11 @@ int tune_search(Run&& run, Rows&& rows, hipStream_t st, Tuned* best_out) {
         *per_sweep = ms_best / ((double)t.T * launches);
         return WMC_OK;
     };
-    // best of `reps` replays of one graph of `launches` launches, per sweep.
-    // The solve replays its launch sequence as a graph; plain launches timed
-    // some shapes up to 4% slower than the solve then ran them, others 1%.
-    // The warm-up launch on st creates whatever the candidate's plan needs,
-    // so that the capture records kernel launches only.
+    // best of `reps` replays of one graph of `launches` launches, per sweep:
+    // the solve replays its launch sequence as a graph, so the final stage
+    // times the candidates the same way.  The warm-up launch on st creates
+    // whatever the candidate's plan needs, so that the capture records
+    // kernel launches only.
     hipStream_t cs = nullptr;
     auto time_graph = [&](const Tuned& t, int launches, int reps, double* per_sweep) -> int {
         int r = run(t.C, t.T, t.R, st);  // warm-up
@@ -757,8 +757,8 @@ int tune_search(Run&& run, Rows&& rows, hipStream_t st, Tuned* best_out) {
     // launches of T sweeps covering at least `sweeps` sweeps
     auto launches_for = [](int T, int sweeps) { return std::max(1, (sweeps + T - 1) / T); };
     const bool verbose = std::getenv("WMC_TUNE_VERBOSE") != nullptr;  // stage timings to stderr
-    // Two stages.  A fresh device first runs about 40 sweeps of one shape so
-    // that its clocks have risen before anything is timed.  Every candidate
+    // Two timed stages.  A fresh device first runs about 40 sweeps of one
+    // shape so that its clocks have risen before anything is timed.  Every candidate
     // is then timed on single launches (best of three), and the six fastest
     // again as graph replays of at least 64 sweeps (best of five), which
     // decide: runs of 32 sweeps, best of three, measured noisier than either
