@@ -203,9 +203,11 @@ int wmc_solve_batched(const wmc_image* imgs, int n_imgs, const float* lam, int i
 
 /* ---------------------------------------------------------------------------
  * wmc_autotune -- times candidate launch shapes (columns per lane, sweeps
- * per residency, rows per work item) on this batch for a few iterations,
- * using ws as scratch and writing nothing else, and returns the fastest in
- * *out.  Results are cached in memory and in the JSON file named by the
+ * per residency, rows per work item) on this batch, using ws as scratch and
+ * writing nothing else, and returns the fastest in *out: after untimed
+ * launches that let the clocks rise, every candidate is timed on single
+ * launches and the six fastest again as graph replays of at least 64
+ * sweeps, which decide (the same search serves wmc_solve's shapes).  Results are cached in memory and in the JSON file named by the
  * environment variable WMC_TUNE_CACHE (default ~/.cache/wmc/tune.json),
  * keyed by device architecture and a size class of the batch.  The
  * environment variable WMC_TUNE=off|cached|force selects defaults only,
