@@ -59,9 +59,10 @@ def kernel_sha():
 
 
 def read_traffic(tuning, side):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source and this launch shape (lines
-    "- hbm_bytes_per_launch[C,T,R]: N")."""
+    """Bytes per launch leaving L2 (FETCH_SIZE + WRITE_SIZE, calibrated; the
+    Infinity Cache's hits included) from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source and this launch
+    shape (lines "- hbm_bytes_per_launch[C,T,R]: N"); else None."""
     path = os.path.join(ROOT, "profiles", f"stream_kernel_{side}_counters.md")
     if not os.path.exists(path):
         return None
